@@ -1,0 +1,222 @@
+/*
+ * wmi.h -- windowed KSG mutual information on AMD MI355X (gfx950): C-ABI.
+ *
+ * The library evaluates, for batches of time windows over pairs of series
+ * held in GPU memory, the KSG estimate of mutual information of Eq. (2)
+ * (Section 4.2 of Ho et al., "A Unified Approach for Multi-Scale Synchronous
+ * Correlation Search in Big Time Series"), and the noise test of
+ * Definition 6.2 for a window split into an overlapping part and a newly
+ * added part (Section 6.2).
+ *
+ * Conventions for every entry point:
+ *   - returns WMI_OK (0) or a negative WMI_E* code; the message of the last
+ *     failure on the calling thread is available from wmi_last_error();
+ *   - pointers named host_* are host memory, d_* are device memory;
+ *   - a NULL required pointer gives WMI_EINVAL;
+ *   - after a HIP runtime error the store is poisoned: that call and every
+ *     later call on the store return WMI_EHIP.
+ *
+ * Numerics: inputs are float32.  Values on the 2^-12 grid with magnitude
+ * below 2^11 give exact neighbour distances and counts; other finite values
+ * are evaluated after rounding to that grid and their results carry
+ * WMI_F_OFFGRID.  NaN and infinities are rejected when a series is added.
+ * Digamma sums are accumulated exactly in 64-bit fixed point (2^-44) and the
+ * estimate is formed in double precision; the noise comparisons are done in
+ * double precision.
+ */
+#ifndef WMI_H
+#define WMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMI_VERSION_MAJOR 0
+#define WMI_VERSION_MINOR 1
+
+/* ---- return codes ------------------------------------------------------ */
+#define WMI_OK 0
+#define WMI_EINVAL (-1)    /* bad argument: id, window range, k, size       */
+#define WMI_ENOMEM (-2)    /* can never fit the memory budget               */
+#define WMI_EBUSY (-3)     /* does not fit now (non-blocking), or in use    */
+#define WMI_ETIMEDOUT (-4) /* wmi_wait timed out; the batch keeps running   */
+#define WMI_EHIP (-5)      /* HIP runtime error; the store is poisoned      */
+#define WMI_ESTATE (-6)    /* call not valid in the object's current state  */
+
+/* ---- limits -------------------------------------------------------------- */
+#define WMI_MAX_WINDOW 4096 /* points per window, including a noise union   */
+#define WMI_MAX_K 16
+
+/* ---- result flags (wmi_result.flags) ------------------------------------- */
+#define WMI_F_NOISE 1u       /* Definition 6.2 holds for the triple          */
+#define WMI_F_TOO_SHORT 2u   /* some window has m <= k: its MI is NaN        */
+#define WMI_F_NONPOS_BASE 4u /* I(w_o) <= 0: Definition 6.2 does not apply   */
+#define WMI_F_OFFGRID 8u     /* some value was off the 2^-12 grid / range    */
+
+/* ---- store flags ----------------------------------------------------------- */
+#define WMI_STORE_STRICT_GRID 1u /* reject off-grid series at add time        */
+
+/* ---- submit flags (wmi_params.flags) ---------------------------------------- */
+#define WMI_SUBMIT_NONBLOCKING 1u /* WMI_EBUSY instead of waiting for memory  */
+#define WMI_SUBMIT_PLAIN 2u       /* one kernel launch per window (baseline)   */
+
+typedef struct wmi_store wmi_store;
+typedef struct wmi_batch wmi_batch;
+
+typedef struct {
+    int device;                /* HIP device ordinal                              */
+    uint32_t flags;            /* WMI_STORE_*                                     */
+    uint64_t hbm_budget_bytes; /* cap on batch-owned device memory; 0 = 1 GiB      */
+} wmi_store_desc;
+
+/*
+ * One query (32 bytes).  Series a supplies the first coordinate x, series b
+ * the second coordinate y, at the same time indices (Definition 3.4).
+ *   ext_side == 0 : one window [start, start + len).
+ *   ext_side == +1: a noise triple; base w_o = [start, start + len), extension
+ *                   w_d = [start + len, start + len + ext_len), union
+ *                   w'' = [start, start + len + ext_len).
+ *   ext_side == -1: as +1 with the extension on the left:
+ *                   w_d = [start - ext_len, start), w'' = [start - ext_len,
+ *                   start + len).
+ * Every window must lie inside both series; len + ext_len <= WMI_MAX_WINDOW.
+ */
+typedef struct {
+    uint32_t a, b;
+    uint64_t start;
+    uint32_t len;
+    uint32_t ext_len;
+    int32_t ext_side;
+    uint32_t reserved; /* must be 0 */
+} wmi_query;
+
+/*
+ * k          : neighbours, 1..WMI_MAX_K (Eq. 2); 4 is the usual choice.
+ * estimator  : 0 = Eq. 2 as printed (per-dimension radii from the k
+ *              neighbours, counts with <=, psi(n_x), -1/k);
+ *              1 = Kraskov's first form (joint radius, counts with <,
+ *              psi(n_x + 1), no -1/k).
+ * tau        : noise threshold of Definition 6.2 (nats).
+ * tau_normalize: 0 compare I(w_d) < tau; 1 compare I(w_d) < tau * ln|w_d|.
+ * flags      : WMI_SUBMIT_*.
+ */
+typedef struct {
+    uint32_t k;
+    uint32_t estimator;
+    double tau;
+    uint32_t tau_normalize;
+    uint32_t flags;
+} wmi_params;
+
+/* One result per query (32 bytes).  mi_ext and mi_union are NaN for plain
+ * windows.  MI values are in nats and are not clamped (KSG can be < 0). */
+typedef struct {
+    double mi_base, mi_ext, mi_union;
+    uint32_t flags;
+    uint32_t reserved;
+} wmi_result;
+
+typedef struct {
+    uint64_t windows;        /* windows evaluated (3 per noise triple)         */
+    uint64_t ordered_pairs;  /* sum of m (m - 1) over those windows            */
+    uint64_t launches;       /* kernel launches used                           */
+    double device_ms;        /* event time from first to last launch           */
+} wmi_batch_stats;
+
+/* Library version as (major << 16) | minor. */
+int wmi_version(void);
+
+/* Message of the last failure on this thread ("" if none).  Valid until the
+ * next failing call on the same thread. */
+const char *wmi_last_error(void);
+
+/* Create a store on a device: uploads the digamma tables (built on the host
+ * from the asymptotic series and the recurrence) and owns all device memory
+ * it allocates.  *out receives the store.  Thread-safe: a store may be used
+ * from several threads. */
+int wmi_store_create(const wmi_store_desc *desc, wmi_store **out);
+
+/* Wait for every batch of the store, free its device memory and the store.
+ * Batches not yet destroyed become invalid. */
+int wmi_store_destroy(wmi_store *store);
+
+/* Copy n float32 values from host memory into a new resident series; the
+ * caller keeps ownership of host_values.  NaN/Inf -> WMI_EINVAL; off-grid
+ * values -> WMI_EINVAL under WMI_STORE_STRICT_GRID.  *id receives the id. */
+int wmi_series_add(wmi_store *store, const float *host_values, uint64_t n, uint32_t *id);
+
+/* Register n float32 values already in device memory (e.g. a torch tensor)
+ * without copying.  The caller keeps d_values alive and unchanged until the
+ * series is removed or the store destroyed.  The values are validated by a
+ * kernel on `stream` (a hipStream_t, or NULL for the store's stream); the
+ * call returns after that check. */
+int wmi_series_add_device(wmi_store *store, const float *d_values, uint64_t n, void *stream,
+                          uint32_t *id);
+
+/* Remove a series.  WMI_EBUSY if an unfinished batch reads it. */
+int wmi_series_remove(wmi_store *store, uint32_t id);
+
+/* Length of a series (WMI_EINVAL for an unknown id). */
+int wmi_series_length(wmi_store *store, uint32_t id, uint64_t *n);
+
+/*
+ * Submit `count` queries (host memory, copied before return) for evaluation
+ * on `stream` (hipStream_t, or NULL for the store's stream).  The batch owns
+ * its device buffers until wmi_batch_destroy.  Returns after enqueueing; the
+ * work is ordered after earlier work on the stream.
+ * Errors: WMI_EINVAL (bad id, window outside a series, len + ext_len above
+ * WMI_MAX_WINDOW, bad k or estimator, reserved field set); WMI_ENOMEM (the
+ * batch needs more than the store's budget even when alone); WMI_EBUSY (the
+ * batch does not fit beside batches in flight and WMI_SUBMIT_NONBLOCKING is
+ * set; without that flag the call waits for memory to free up).
+ */
+int wmi_submit(wmi_store *store, const wmi_query *host_queries, uint64_t count,
+               const wmi_params *params, void *stream, wmi_batch **out);
+
+/* Wait up to timeout_us microseconds (< 0: forever) for a batch to finish.
+ * WMI_ETIMEDOUT leaves the batch running. */
+int wmi_wait(wmi_batch *batch, int64_t timeout_us);
+
+/* Nonzero if the batch has finished (does not block). */
+int wmi_done(wmi_batch *batch);
+
+/* Wait for the batch, then copy its `count` results to host_out. */
+int wmi_read(wmi_batch *batch, wmi_result *host_out);
+
+/*
+ * Run the batch's work again, unchanged, on `stream` (NULL: the stream it was
+ * submitted on): descriptor upload, kernels and result download are captured
+ * once into a HIP graph and replayed.  Results are overwritten with the same
+ * values.  The batch must be finished; WMI_SUBMIT_PLAIN batches are replayed
+ * launch by launch without a graph.
+ */
+int wmi_batch_replay(wmi_batch *batch, void *stream);
+
+/* Counters and device time of a finished batch (of its last run). */
+int wmi_batch_stats_get(wmi_batch *batch, wmi_batch_stats *out);
+
+/* Wait for the batch and release it (NULL is accepted). */
+int wmi_batch_destroy(wmi_batch *batch);
+
+/*
+ * Per-point export of one window for exact parity tests: evaluates the base
+ * window of *query (ext fields ignored) and writes, for point i of the
+ * window, the marginal counts nx[i], ny[i] and the radii eps_x[i], eps_y[i]
+ * (estimator 0: largest |dx|, |dy| over the k neighbours; estimator 1: the
+ * joint k-th distance in both), each host arrays of query->len elements.
+ * Synchronous.
+ */
+int wmi_debug_window(wmi_store *store, const wmi_query *query, const wmi_params *params,
+                     uint32_t *host_nx, uint32_t *host_ny, float *host_eps_x, float *host_eps_y);
+
+/* Copy the library's double-precision digamma table psi(1..n) (n <= 8192)
+ * to host_out (for checks against an independent construction). */
+int wmi_psi_table(uint32_t n, double *host_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMI_H */

@@ -1,0 +1,87 @@
+// wmi_internal.h -- device-side descriptors shared by the runtime and kernels.
+//
+// HBM layout of one launch (all arrays carved from one batch allocation):
+//   WinDesc  win[W]      one per window (a noise triple contributes three)
+//   Item     item[I]     kNN work items: (window, first query point); sorted by
+//                        cost m * points, largest first, for the persistent form
+//   QDesc    qd[Qn]      one per query: its first window, window count, tau
+//   int32    sorted[2*P] per window, its x and y grid integers in ascending
+//                        order (P = sum of m); written by the prep kernel
+//   WinAux   aux[W]      per window: grid minima, key width, off-grid flag
+//   u64      acc[W]      fixed-point digamma sums (2^-44), integer atomics
+//   u32      wdone[W], qdone[Qn], counter[1]   completion and work counters
+//   double   wmi[W]; u32 wflags[W]           per-window estimate and flags
+//   Result   res[Qn]     32-byte results, copied back to the host
+#pragma once
+#include <stdint.h>
+
+namespace wmi {
+
+constexpr int kMaxWindow = 4096;
+constexpr int kMaxK = 16;
+constexpr int kPsiMax = 8192;         // psi tables cover 1..kPsiMax
+constexpr int kBlock = 256;           // threads per workgroup
+constexpr int kFixShift = 44;         // fixed-point scale of the digamma sums
+
+constexpr uint32_t kFlagNoise = 1u, kFlagTooShort = 2u, kFlagNonPos = 4u, kFlagOffGrid = 8u;
+
+struct WinDesc {            // 32 bytes
+    const float *x;         // series a + window start
+    const float *y;         // series b + window start
+    uint32_t m;             // points in the window
+    uint32_t query;         // owning query (index within the launch)
+    uint32_t sorted_off;    // offset of this window's sorted arrays (in points)
+    uint32_t n_items;       // kNN items covering the window's points
+};
+
+struct Item {               // 8 bytes
+    uint32_t win;
+    uint32_t q0;            // first query point of the item
+};
+
+struct QDesc {              // 16 bytes
+    uint32_t win0;          // first window of the query
+    uint32_t nwin;          // 1 (plain window) or 3 (base, extension, union)
+    double tau_eff;         // noise threshold, already normalised if requested
+};
+
+struct WinAux {             // 16 bytes
+    int32_t min_x, min_y;   // window minima of the grid integers
+    uint32_t nb;            // index bits in a 32-bit key; 0 selects 64-bit keys
+    uint32_t flags;         // kFlagOffGrid
+};
+
+struct Result {             // 32 bytes, same layout as wmi_result
+    double mi_base, mi_ext, mi_union;
+    uint32_t flags, reserved;
+};
+
+struct LaunchArgs {
+    const WinDesc *win;
+    const Item *item;
+    const QDesc *qd;
+    int32_t *sorted;
+    WinAux *aux;
+    unsigned long long *acc;
+    uint32_t *wdone;
+    uint32_t *qdone;
+    uint32_t *counter;
+    double *wmi;
+    uint32_t *wflags;
+    Result *res;
+    const double *psi_d;          // psi(n) in double, index n (0 unused)
+    const long long *psi_fix;     // round(psi(n) * 2^44), index n (0 unused)
+    uint32_t n_win;
+    uint32_t n_items;
+    uint32_t n_query;
+    uint32_t item_begin;          // first item of this launch
+    uint32_t k;
+    uint32_t estimator;
+    uint32_t persistent;          // 1: take items from *counter; 0: blockIdx.x
+    uint32_t win_begin;           // prep kernel: first window of this launch
+    // debug export (one window): per point counts and radii, or null
+    uint32_t *dbg_nx, *dbg_ny;
+    float *dbg_ex, *dbg_ey;
+};
+
+}  // namespace wmi

@@ -1,0 +1,922 @@
+// wmi_runtime.cpp -- host runtime behind the C-ABI of include/wmi.h.
+//
+// A store holds resident series on one device, the digamma tables and a
+// memory budget.  A submit validates queries, expands noise triples into
+// their three windows (Definition 6.2 as applied in Section 6.2: overlap,
+// newly added part, union), builds the window and work-item descriptors in
+// pinned host memory, and enqueues on one stream:
+//   descriptor upload -> clear -> prep (sort) -> persistent main -> result download
+// Work items are (window, block of 512 query points); the persistent kernel
+// takes them largest-first from an atomic counter.  A batch can be replayed as
+// a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "wmi.h"
+#include "wmi_internal.h"
+
+namespace wmi {
+hipError_t launch_clear(const LaunchArgs &a, hipStream_t s);
+hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s);
+hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s);
+int main_occupancy(uint32_t k);
+void build_psi_tables(int n_max, std::vector<double> &psi_d, std::vector<long long> &psi_fix);
+}  // namespace wmi
+
+using namespace wmi;
+
+static_assert(sizeof(wmi_query) == 32, "wmi_query layout");
+static_assert(sizeof(wmi_result) == 32 && sizeof(Result) == 32, "result layout");
+static_assert(sizeof(WinDesc) == 32 && sizeof(Item) == 8 && sizeof(QDesc) == 16, "descriptors");
+
+namespace {
+
+constexpr uint32_t kItemPoints = 2 * kBlock;  // query points per work item
+constexpr uint64_t kDefaultBudget = 1ull << 30;
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+struct Series {
+    const float *d = nullptr;
+    uint64_t n = 0;
+    bool owned = false;
+    bool live = false;
+    bool offgrid = false;
+    uint32_t busy = 0;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct wmi_store {
+    int device = 0;
+    uint32_t flags = 0;
+    uint64_t budget = kDefaultBudget;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    double *psi_d = nullptr;
+    long long *psi_fix = nullptr;
+    int cu_count = 1;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Series> series;
+    uint64_t inflight = 0;
+    bool poisoned = false;
+    std::string poison_msg;
+    std::set<wmi_batch *> batches;
+};
+
+struct wmi_batch {
+    wmi_store *st = nullptr;
+    uint64_t count = 0;
+    hipStream_t stream = nullptr;
+    wmi_params params{};
+    // device buffer and its layout
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    bool budget_held = false;
+    // pinned host buffer: descriptors followed by results
+    char *host = nullptr;
+    size_t host_bytes = 0;
+    size_t desc_bytes = 0;  // uploaded prefix
+    LaunchArgs args{};
+    uint32_t grid = 0;
+    std::vector<uint32_t> win_first_item;  // plain form: first item of each window
+    Result *h_res = nullptr;
+    Result *d_res = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_end = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint32_t> series_used;
+    wmi_batch_stats stats{};
+    std::atomic<int> complete{0};  // set by the stream callback after the download
+    bool enqueued = false;         // the last run was fully enqueued (callback + event)
+    bool finished = false;         // completion observed by the owner (stats read)
+    bool series_released = false;
+};
+
+namespace {
+
+int poison(wmi_store *st, hipError_t e, const char *what)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    st->poisoned = true;
+    st->poison_msg = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(WMI_EHIP, "%s", st->poison_msg.c_str());
+}
+
+#define HIPCHK(st, expr)                          \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess)                     \
+            return poison((st), e_, #expr);       \
+    } while (0)
+
+int check_poison(wmi_store *st)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    if (st->poisoned)
+        return fail(WMI_EHIP, "store poisoned by an earlier HIP error: %s", st->poison_msg.c_str());
+    return WMI_OK;
+}
+
+bool value_on_grid(float v)
+{
+    double s = (double)v * 4096.0;
+    return std::isfinite(s) && s == std::nearbyint(s) && std::fabs(s) <= 8388607.0;
+}
+
+// Release the series pins and the memory budget of a finished batch.
+void release_batch_resources(wmi_batch *b)
+{
+    wmi_store *st = b->st;
+    std::lock_guard<std::mutex> lk(st->mu);
+    if (!b->series_released) {
+        for (uint32_t id : b->series_used)
+            if (id < st->series.size() && st->series[id].busy)
+                st->series[id].busy--;
+        b->series_released = true;
+    }
+    if (b->budget_held) {
+        st->inflight -= b->dev_bytes;
+        b->budget_held = false;
+    }
+    st->cv.notify_all();
+}
+
+int enqueue_work(wmi_batch *b, hipStream_t s)
+{
+    wmi_store *st = b->st;
+    const LaunchArgs &a = b->args;
+    if (b->desc_bytes)
+        HIPCHK(st, hipMemcpyAsync(b->dev, b->host, b->desc_bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(st, launch_clear(a, s));
+    if (b->params.flags & WMI_SUBMIT_PLAIN) {
+        // baseline form: every window is its own prep launch and main launch
+        for (uint32_t w = 0; w < a.n_win; ++w) {
+            LaunchArgs aw = a;
+            aw.win_begin = w;
+            HIPCHK(st, launch_prep(aw, 1, s));
+            aw.item_begin = b->win_first_item[w];
+            aw.n_items = b->win_first_item[w + 1] - b->win_first_item[w];
+            aw.persistent = 0;
+            HIPCHK(st, launch_main(aw, aw.n_items, s));
+        }
+    } else {
+        HIPCHK(st, launch_prep(a, a.n_win, s));
+        HIPCHK(st, launch_main(a, b->grid, s));
+    }
+    if (b->count)
+        HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->count * sizeof(Result), hipMemcpyDeviceToHost, s));
+    return WMI_OK;
+}
+
+// Runs on a HIP runtime thread once everything enqueued before it on the
+// stream has finished: releases the batch's memory budget and series pins.
+void on_batch_complete(void *user)
+{
+    wmi_batch *b = static_cast<wmi_batch *>(user);
+    release_batch_resources(b);
+    b->complete.store(1, std::memory_order_release);
+}
+
+int run_batch(wmi_batch *b, hipStream_t s)
+{
+    wmi_store *st = b->st;
+    b->complete.store(0, std::memory_order_relaxed);
+    b->enqueued = false;
+    HIPCHK(st, hipEventRecord(b->ev_k0, s));
+    if (b->graph_exec) {
+        HIPCHK(st, hipGraphLaunch(b->graph_exec, s));
+    } else {
+        int rc = enqueue_work(b, s);
+        if (rc)
+            return rc;
+    }
+    HIPCHK(st, hipEventRecord(b->ev_k1, s));
+    HIPCHK(st, hipLaunchHostFunc(s, on_batch_complete, b));
+    HIPCHK(st, hipEventRecord(b->ev_end, s));
+    b->enqueued = true;
+    b->finished = false;
+    b->stats.launches = (b->params.flags & WMI_SUBMIT_PLAIN) ? 1 + 2ull * b->args.n_win : 3;
+    return WMI_OK;
+}
+
+int finish_if_done(wmi_batch *b, bool block, int64_t timeout_us)
+{
+    if (b->finished)
+        return WMI_OK;
+    wmi_store *st = b->st;
+    if (!b->enqueued)
+        return fail(WMI_ESTATE, "batch was not fully enqueued");
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        hipError_t e = hipEventQuery(b->ev_end);
+        if (e == hipSuccess && b->complete.load(std::memory_order_acquire))
+            break;
+        if (e != hipSuccess && e != hipErrorNotReady)
+            return poison(st, e, "hipEventQuery");
+        if (!block)
+            return WMI_ETIMEDOUT;
+        if (timeout_us >= 0) {
+            auto el = std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0);
+            if (el.count() >= timeout_us)
+                return fail(WMI_ETIMEDOUT, "batch not finished after %lld us", (long long)timeout_us);
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, b->ev_k0, b->ev_k1) == hipSuccess)
+        b->stats.device_ms = ms;
+    b->finished = true;
+    return WMI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+int wmi_version(void) { return (WMI_VERSION_MAJOR << 16) | WMI_VERSION_MINOR; }
+
+const char *wmi_last_error(void) { return g_err.c_str(); }
+
+int wmi_psi_table(uint32_t n, double *host_out)
+{
+    if (!host_out || n < 1 || n > (uint32_t)kPsiMax)
+        return fail(WMI_EINVAL, "wmi_psi_table: n must be in 1..%d", kPsiMax);
+    std::vector<double> d;
+    std::vector<long long> f;
+    build_psi_tables(kPsiMax, d, f);
+    for (uint32_t i = 0; i < n; ++i)
+        host_out[i] = d[i + 1];
+    return WMI_OK;
+}
+
+int wmi_store_create(const wmi_store_desc *desc, wmi_store **out)
+{
+    if (!desc || !out)
+        return fail(WMI_EINVAL, "wmi_store_create: null argument");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(WMI_EHIP, "wmi_store_create: no HIP device available");
+    if (desc->device < 0 || desc->device >= ndev)
+        return fail(WMI_EINVAL, "wmi_store_create: device %d out of range (%d devices)", desc->device, ndev);
+    if (desc->flags & ~WMI_STORE_STRICT_GRID)
+        return fail(WMI_EINVAL, "wmi_store_create: unknown flags 0x%x", desc->flags);
+    DeviceGuard g(desc->device);
+    if (!g.ok)
+        return fail(WMI_EHIP, "wmi_store_create: hipSetDevice(%d) failed", desc->device);
+    wmi_store *st = new wmi_store();
+    st->device = desc->device;
+    st->flags = desc->flags;
+    st->budget = desc->hbm_budget_bytes ? desc->hbm_budget_bytes : kDefaultBudget;
+    hipError_t e = hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&st->capture_stream, hipStreamNonBlocking);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess)
+        e = hipGetDeviceProperties(&prop, st->device);
+    if (e == hipSuccess)
+        st->cu_count = prop.multiProcessorCount;
+    std::vector<double> pd;
+    std::vector<long long> pf;
+    build_psi_tables(kPsiMax, pd, pf);
+    if (e == hipSuccess)
+        e = hipMalloc(&st->psi_d, pd.size() * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc(&st->psi_fix, pf.size() * sizeof(long long));
+    if (e == hipSuccess)
+        e = hipMemcpy(st->psi_d, pd.data(), pd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(st->psi_fix, pf.data(), pf.size() * sizeof(long long), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int rc = fail(WMI_EHIP, "wmi_store_create: %s", hipGetErrorString(e));
+        if (st->psi_d) (void)hipFree(st->psi_d);
+        if (st->psi_fix) (void)hipFree(st->psi_fix);
+        if (st->stream) (void)hipStreamDestroy(st->stream);
+        if (st->capture_stream) (void)hipStreamDestroy(st->capture_stream);
+        delete st;
+        return rc;
+    }
+    *out = st;
+    return WMI_OK;
+}
+
+int wmi_batch_destroy(wmi_batch *b);
+
+int wmi_store_destroy(wmi_store *st)
+{
+    if (!st)
+        return fail(WMI_EINVAL, "wmi_store_destroy: null store");
+    DeviceGuard g(st->device);
+    std::vector<wmi_batch *> bs;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        bs.assign(st->batches.begin(), st->batches.end());
+    }
+    for (wmi_batch *b : bs)
+        wmi_batch_destroy(b);
+    (void)hipStreamSynchronize(st->stream);
+    for (Series &s : st->series)
+        if (s.live && s.owned)
+            (void)hipFree((void *)s.d);
+    (void)hipFree(st->psi_d);
+    (void)hipFree(st->psi_fix);
+    (void)hipStreamDestroy(st->stream);
+    (void)hipStreamDestroy(st->capture_stream);
+    delete st;
+    return WMI_OK;
+}
+
+static int add_series_entry(wmi_store *st, const float *d, uint64_t n, bool owned, bool offgrid, uint32_t *id)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    Series s;
+    s.d = d;
+    s.n = n;
+    s.owned = owned;
+    s.live = true;
+    s.offgrid = offgrid;
+    st->series.push_back(s);
+    *id = (uint32_t)(st->series.size() - 1);
+    return WMI_OK;
+}
+
+int wmi_series_add(wmi_store *st, const float *host_values, uint64_t n, uint32_t *id)
+{
+    if (!st || !host_values || !id)
+        return fail(WMI_EINVAL, "wmi_series_add: null argument");
+    if (n == 0)
+        return fail(WMI_EINVAL, "wmi_series_add: empty series");
+    if (int rc = check_poison(st))
+        return rc;
+    bool off = false;
+    for (uint64_t i = 0; i < n; ++i) {
+        float v = host_values[i];
+        if (!std::isfinite(v))
+            return fail(WMI_EINVAL, "wmi_series_add: value %llu is not finite", (unsigned long long)i);
+        if (!off && !value_on_grid(v))
+            off = true;
+    }
+    if (off && (st->flags & WMI_STORE_STRICT_GRID))
+        return fail(WMI_EINVAL, "wmi_series_add: values off the 2^-12 grid (strict store)");
+    DeviceGuard g(st->device);
+    float *d = nullptr;
+    HIPCHK(st, hipMalloc(&d, n * sizeof(float)));
+    hipError_t e = hipMemcpy(d, host_values, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return poison(st, e, "hipMemcpy(series)");
+    }
+    return add_series_entry(st, d, n, true, off, id);
+}
+
+int wmi_series_add_device(wmi_store *st, const float *d_values, uint64_t n, void *stream, uint32_t *id)
+{
+    if (!st || !d_values || !id)
+        return fail(WMI_EINVAL, "wmi_series_add_device: null argument");
+    if (n == 0)
+        return fail(WMI_EINVAL, "wmi_series_add_device: empty series");
+    if (int rc = check_poison(st))
+        return rc;
+    DeviceGuard g(st->device);
+    hipStream_t s = stream ? (hipStream_t)stream : st->stream;
+    unsigned long long *bad = nullptr;
+    HIPCHK(st, hipMalloc(&bad, 2 * sizeof(unsigned long long)));
+    unsigned long long hbad[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(bad, hbad, sizeof hbad, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_validate(d_values, n, bad, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    (void)hipFree(bad);
+    if (e != hipSuccess)
+        return poison(st, e, "validate series");
+    if (hbad[0])
+        return fail(WMI_EINVAL, "wmi_series_add_device: %llu values are not finite", hbad[0]);
+    if (hbad[1] && (st->flags & WMI_STORE_STRICT_GRID))
+        return fail(WMI_EINVAL, "wmi_series_add_device: %llu values off the 2^-12 grid (strict store)", hbad[1]);
+    return add_series_entry(st, d_values, n, false, hbad[1] != 0, id);
+}
+
+int wmi_series_remove(wmi_store *st, uint32_t id)
+{
+    if (!st)
+        return fail(WMI_EINVAL, "wmi_series_remove: null store");
+    const float *to_free = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        if (id >= st->series.size() || !st->series[id].live)
+            return fail(WMI_EINVAL, "wmi_series_remove: unknown series %u", id);
+        if (st->series[id].busy)
+            return fail(WMI_EBUSY, "wmi_series_remove: series %u is read by %u unfinished batches", id,
+                        st->series[id].busy);
+        if (st->series[id].owned)
+            to_free = st->series[id].d;
+        st->series[id].live = false;
+        st->series[id].d = nullptr;
+    }
+    if (to_free) {
+        DeviceGuard g(st->device);
+        HIPCHK(st, hipFree((void *)to_free));
+    }
+    return WMI_OK;
+}
+
+int wmi_series_length(wmi_store *st, uint32_t id, uint64_t *n)
+{
+    if (!st || !n)
+        return fail(WMI_EINVAL, "wmi_series_length: null argument");
+    std::lock_guard<std::mutex> lk(st->mu);
+    if (id >= st->series.size() || !st->series[id].live)
+        return fail(WMI_EINVAL, "wmi_series_length: unknown series %u", id);
+    *n = st->series[id].n;
+    return WMI_OK;
+}
+
+static int validate_params(const wmi_params *p)
+{
+    if (p->k < 1 || p->k > WMI_MAX_K)
+        return fail(WMI_EINVAL, "k = %u outside 1..%d", p->k, WMI_MAX_K);
+    if (p->estimator > 1)
+        return fail(WMI_EINVAL, "estimator %u unknown (0 or 1)", p->estimator);
+    if (p->tau_normalize > 1)
+        return fail(WMI_EINVAL, "tau_normalize must be 0 or 1");
+    if (p->flags & ~(WMI_SUBMIT_NONBLOCKING | WMI_SUBMIT_PLAIN))
+        return fail(WMI_EINVAL, "unknown submit flags 0x%x", p->flags);
+    if (!std::isfinite(p->tau))
+        return fail(WMI_EINVAL, "tau must be finite");
+    return WMI_OK;
+}
+
+// window list of one query: (start, m) for base, extension, union
+static int query_windows(const wmi_query &q, const std::vector<Series> &ser, uint64_t idx, uint64_t st[3],
+                         uint32_t m[3], uint32_t *nwin)
+{
+    if (q.reserved)
+        return fail(WMI_EINVAL, "query %llu: reserved field must be 0", (unsigned long long)idx);
+    if (q.a >= ser.size() || !ser[q.a].live || q.b >= ser.size() || !ser[q.b].live)
+        return fail(WMI_EINVAL, "query %llu: unknown series id (%u, %u)", (unsigned long long)idx, q.a, q.b);
+    const uint64_t n = std::min(ser[q.a].n, ser[q.b].n);
+    if (q.len == 0)
+        return fail(WMI_EINVAL, "query %llu: empty window", (unsigned long long)idx);
+    if (q.ext_side == 0) {
+        if (q.len > (uint32_t)WMI_MAX_WINDOW)
+            return fail(WMI_EINVAL, "query %llu: window of %u points exceeds %d", (unsigned long long)idx, q.len,
+                        WMI_MAX_WINDOW);
+        if (q.start > n || q.len > n - q.start)
+            return fail(WMI_EINVAL, "query %llu: window [%llu, +%u) outside series of %llu points",
+                        (unsigned long long)idx, (unsigned long long)q.start, q.len, (unsigned long long)n);
+        st[0] = q.start;
+        m[0] = q.len;
+        *nwin = 1;
+        return WMI_OK;
+    }
+    if (q.ext_side != 1 && q.ext_side != -1)
+        return fail(WMI_EINVAL, "query %llu: ext_side must be -1, 0 or +1", (unsigned long long)idx);
+    if (q.ext_len == 0)
+        return fail(WMI_EINVAL, "query %llu: empty extension", (unsigned long long)idx);
+    if ((uint64_t)q.len + q.ext_len > (uint64_t)WMI_MAX_WINDOW)
+        return fail(WMI_EINVAL, "query %llu: union of %llu points exceeds %d", (unsigned long long)idx,
+                    (unsigned long long)q.len + q.ext_len, WMI_MAX_WINDOW);
+    uint64_t lo = q.ext_side > 0 ? q.start : q.start - q.ext_len;
+    if (q.ext_side < 0 && q.start < q.ext_len)
+        return fail(WMI_EINVAL, "query %llu: left extension before the series start", (unsigned long long)idx);
+    uint64_t total = (uint64_t)q.len + q.ext_len;
+    if (lo > n || total > n - lo)
+        return fail(WMI_EINVAL, "query %llu: triple outside series of %llu points", (unsigned long long)idx,
+                    (unsigned long long)n);
+    st[0] = q.start;
+    m[0] = q.len;
+    st[1] = q.ext_side > 0 ? q.start + q.len : q.start - q.ext_len;
+    m[1] = q.ext_len;
+    st[2] = lo;
+    m[2] = (uint32_t)total;
+    *nwin = 3;
+    return WMI_OK;
+}
+
+int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,
+               wmi_batch **out)
+{
+    if (!st || !p || !out || (count && !qs))
+        return fail(WMI_EINVAL, "wmi_submit: null argument");
+    *out = nullptr;
+    if (int rc = validate_params(p))
+        return rc;
+    if (count > 0xFFFFFFF0ull)
+        return fail(WMI_EINVAL, "wmi_submit: too many queries in one batch");
+    if (int rc = check_poison(st))
+        return rc;
+    DeviceGuard g(st->device);
+
+    // ---- validate and size ------------------------------------------------
+    std::vector<Series> ser;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        ser = st->series;
+    }
+    uint64_t n_win = 0, n_pts = 0, n_items = 0, pairs = 0;
+    std::vector<uint32_t> used;
+    for (uint64_t t = 0; t < count; ++t) {
+        uint64_t s3[3];
+        uint32_t m3[3], nw = 0;
+        if (int rc = query_windows(qs[t], ser, t, s3, m3, &nw))
+            return rc;
+        for (uint32_t r = 0; r < nw; ++r) {
+            n_win++;
+            n_pts += m3[r];
+            n_items += std::max<uint64_t>(1, (m3[r] + kItemPoints - 1) / kItemPoints);
+            pairs += (uint64_t)m3[r] * (m3[r] - 1);
+        }
+        used.push_back(qs[t].a);
+        used.push_back(qs[t].b);
+    }
+    if (n_win > 0xFFFFFFF0ull || n_pts > 0xFFFFFFF0ull || n_items > 0xFFFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu windows, %llu points)",
+                    (unsigned long long)n_win, (unsigned long long)n_pts);
+    std::sort(used.begin(), used.end());
+    used.erase(std::unique(used.begin(), used.end()), used.end());
+
+    // ---- layout -------------------------------------------------------------
+    const size_t A = 256;
+    size_t o_win = 0;
+    size_t o_item = align_up(o_win + n_win * sizeof(WinDesc), A);
+    size_t o_qd = align_up(o_item + n_items * sizeof(Item), A);
+    size_t desc_bytes = align_up(o_qd + count * sizeof(QDesc), A);
+    size_t o_sorted = desc_bytes;
+    size_t o_aux = align_up(o_sorted + 2 * n_pts * sizeof(int32_t), A);
+    size_t o_acc = align_up(o_aux + n_win * sizeof(WinAux), A);
+    size_t o_wdone = align_up(o_acc + n_win * sizeof(unsigned long long), A);
+    size_t o_qdone = align_up(o_wdone + n_win * sizeof(uint32_t), A);
+    size_t o_counter = align_up(o_qdone + count * sizeof(uint32_t), A);
+    size_t o_wmi = align_up(o_counter + sizeof(uint32_t), A);
+    size_t o_wflags = align_up(o_wmi + n_win * sizeof(double), A);
+    size_t o_res = align_up(o_wflags + n_win * sizeof(uint32_t), A);
+    size_t dev_bytes = align_up(o_res + count * sizeof(Result), A);
+
+    if (dev_bytes > st->budget)
+        return fail(WMI_ENOMEM, "wmi_submit: batch needs %zu bytes of device memory, budget is %llu", dev_bytes,
+                    (unsigned long long)st->budget);
+    {
+        std::unique_lock<std::mutex> lk(st->mu);
+        if (st->inflight + dev_bytes > st->budget) {
+            if (p->flags & WMI_SUBMIT_NONBLOCKING)
+                return fail(WMI_EBUSY, "wmi_submit: %zu bytes do not fit beside %llu in flight (budget %llu)",
+                            dev_bytes, (unsigned long long)st->inflight, (unsigned long long)st->budget);
+            // running batches release their budget from the stream callback
+            st->cv.wait(lk, [&] { return st->inflight + dev_bytes <= st->budget; });
+        }
+        for (uint32_t id : used) {
+            if (id >= st->series.size() || !st->series[id].live)
+                return fail(WMI_EINVAL, "wmi_submit: series %u removed during submit", id);
+            st->series[id].busy++;
+        }
+        st->inflight += dev_bytes;
+    }
+
+    wmi_batch *b = new wmi_batch();
+    b->st = st;
+    b->count = count;
+    b->params = *p;
+    b->stream = stream ? (hipStream_t)stream : st->stream;
+    b->series_used = used;
+    b->budget_held = true;
+    b->dev_bytes = dev_bytes;
+    b->desc_bytes = desc_bytes;
+    b->stats.windows = n_win;
+    b->stats.ordered_pairs = pairs;
+
+    auto bail = [&](hipError_t e, const char *what) {
+        int rc = poison(st, e, what);
+        release_batch_resources(b);
+        if (b->dev) (void)hipFree(b->dev);
+        if (b->host) (void)hipHostFree(b->host);
+        delete b;
+        return rc;
+    };
+    hipError_t e = hipMalloc(&b->dev, dev_bytes);
+    if (e != hipSuccess)
+        return bail(e, "hipMalloc(batch)");
+    b->host_bytes = desc_bytes + align_up(count * sizeof(Result), A);
+    e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, A), hipHostMallocDefault);
+    if (e != hipSuccess)
+        return bail(e, "hipHostMalloc(batch)");
+    for (hipEvent_t *ev : {&b->ev_k0, &b->ev_k1, &b->ev_end}) {
+        e = hipEventCreate(ev);
+        if (e != hipSuccess)
+            return bail(e, "hipEventCreate");
+    }
+
+    // ---- descriptors --------------------------------------------------------
+    WinDesc *hw = reinterpret_cast<WinDesc *>(b->host + o_win);
+    Item *hi = reinterpret_cast<Item *>(b->host + o_item);
+    QDesc *hq = reinterpret_cast<QDesc *>(b->host + o_qd);
+    b->h_res = reinterpret_cast<Result *>(b->host + desc_bytes);
+    const bool plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
+    uint32_t w = 0;
+    uint64_t pts = 0;
+    std::vector<Item> items;
+    items.reserve(n_items);
+    if (plain)
+        b->win_first_item.reserve(n_win + 1);
+    for (uint64_t t = 0; t < count; ++t) {
+        uint64_t s3[3];
+        uint32_t m3[3], nw = 0;
+        query_windows(qs[t], ser, t, s3, m3, &nw);
+        hq[t].win0 = w;
+        hq[t].nwin = nw;
+        hq[t].tau_eff = p->tau_normalize ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
+        for (uint32_t r = 0; r < nw; ++r, ++w) {
+            WinDesc &d = hw[w];
+            d.x = ser[qs[t].a].d + s3[r];
+            d.y = ser[qs[t].b].d + s3[r];
+            d.m = m3[r];
+            d.query = (uint32_t)t;
+            d.sorted_off = (uint32_t)pts;
+            uint32_t ni = std::max<uint32_t>(1, (m3[r] + kItemPoints - 1) / kItemPoints);
+            d.n_items = ni;
+            if (plain)
+                b->win_first_item.push_back((uint32_t)items.size());
+            for (uint32_t it = 0; it < ni; ++it)
+                items.push_back(Item{w, it * kItemPoints});
+            pts += m3[r];
+        }
+    }
+    if (plain) {
+        b->win_first_item.push_back((uint32_t)items.size());
+        std::copy(items.begin(), items.end(), hi);
+    } else {
+        // largest first (cost = points in the item x window size); a stable
+        // bucket order by log2(cost) is enough for the greedy schedule
+        std::vector<uint32_t> cnt(65, 0);
+        auto bucket = [&](const Item &it) {
+            uint64_t m = hw[it.win].m;
+            uint64_t c = std::min<uint64_t>(kItemPoints, m - it.q0) * m;
+            int lb = 63 - __builtin_clzll(c | 1ull);
+            return 63 - lb;
+        };
+        for (const Item &it : items)
+            cnt[bucket(it) + 1]++;
+        for (int i = 1; i <= 64; ++i)
+            cnt[i] += cnt[i - 1];
+        for (const Item &it : items)
+            hi[cnt[bucket(it)]++] = it;
+    }
+
+    // ---- launch arguments -----------------------------------------------------
+    LaunchArgs &a = b->args;
+    a.win = reinterpret_cast<const WinDesc *>(b->dev + o_win);
+    a.item = reinterpret_cast<const Item *>(b->dev + o_item);
+    a.qd = reinterpret_cast<const QDesc *>(b->dev + o_qd);
+    a.sorted = reinterpret_cast<int32_t *>(b->dev + o_sorted);
+    a.aux = reinterpret_cast<WinAux *>(b->dev + o_aux);
+    a.acc = reinterpret_cast<unsigned long long *>(b->dev + o_acc);
+    a.wdone = reinterpret_cast<uint32_t *>(b->dev + o_wdone);
+    a.qdone = reinterpret_cast<uint32_t *>(b->dev + o_qdone);
+    a.counter = reinterpret_cast<uint32_t *>(b->dev + o_counter);
+    a.wmi = reinterpret_cast<double *>(b->dev + o_wmi);
+    a.wflags = reinterpret_cast<uint32_t *>(b->dev + o_wflags);
+    a.res = reinterpret_cast<Result *>(b->dev + o_res);
+    a.psi_d = st->psi_d;
+    a.psi_fix = st->psi_fix;
+    a.n_win = (uint32_t)n_win;
+    a.n_items = (uint32_t)n_items;
+    a.n_query = (uint32_t)count;
+    a.item_begin = 0;
+    a.k = p->k;
+    a.estimator = p->estimator;
+    a.persistent = 1;
+    a.win_begin = 0;
+    b->d_res = a.res;
+    int occ = main_occupancy(p->k);
+    uint64_t slots = (uint64_t)st->cu_count * (uint64_t)occ;
+    b->grid = (uint32_t)std::min<uint64_t>(n_items, slots);
+
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        st->batches.insert(b);
+    }
+    int rc = run_batch(b, b->stream);
+    if (rc) {
+        (void)hipStreamSynchronize(b->stream);
+        wmi_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return WMI_OK;
+}
+
+int wmi_wait(wmi_batch *b, int64_t timeout_us)
+{
+    if (!b)
+        return fail(WMI_EINVAL, "wmi_wait: null batch");
+    DeviceGuard g(b->st->device);
+    return finish_if_done(b, true, timeout_us);
+}
+
+int wmi_done(wmi_batch *b)
+{
+    if (!b)
+        return 0;
+    DeviceGuard g(b->st->device);
+    return finish_if_done(b, false, 0) == WMI_OK ? 1 : 0;
+}
+
+int wmi_read(wmi_batch *b, wmi_result *out)
+{
+    if (!b || (!out && b->count))
+        return fail(WMI_EINVAL, "wmi_read: null argument");
+    DeviceGuard g(b->st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    if (b->count)
+        std::memcpy(out, b->h_res, b->count * sizeof(Result));
+    return WMI_OK;
+}
+
+int wmi_batch_replay(wmi_batch *b, void *stream)
+{
+    if (!b)
+        return fail(WMI_EINVAL, "wmi_batch_replay: null batch");
+    wmi_store *st = b->st;
+    DeviceGuard g(st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    if (int rc = check_poison(st))
+        return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : b->stream;
+    {
+        // a replay holds the batch's budget and series pins again
+        std::lock_guard<std::mutex> lk(st->mu);
+        for (uint32_t id : b->series_used) {
+            if (id >= st->series.size() || !st->series[id].live)
+                return fail(WMI_ESTATE, "wmi_batch_replay: series %u was removed", id);
+        }
+        for (uint32_t id : b->series_used)
+            st->series[id].busy++;
+        b->series_released = false;
+        st->inflight += b->dev_bytes;
+        b->budget_held = true;
+    }
+    if (!(b->params.flags & WMI_SUBMIT_PLAIN) && !b->graph_exec) {
+        HIPCHK(st, hipStreamBeginCapture(st->capture_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_work(b, st->capture_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st->capture_stream, &graph);
+        if (rc)
+            return rc;
+        if (e != hipSuccess)
+            return poison(st, e, "hipStreamEndCapture");
+        b->graph = graph;
+        HIPCHK(st, hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0));
+    }
+    return run_batch(b, s);
+}
+
+int wmi_batch_stats_get(wmi_batch *b, wmi_batch_stats *out)
+{
+    if (!b || !out)
+        return fail(WMI_EINVAL, "wmi_batch_stats_get: null argument");
+    DeviceGuard g(b->st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    *out = b->stats;
+    return WMI_OK;
+}
+
+int wmi_batch_destroy(wmi_batch *b)
+{
+    if (!b)
+        return WMI_OK;
+    wmi_store *st = b->st;
+    DeviceGuard g(st->device);
+    (void)hipEventSynchronize(b->ev_end);
+    (void)finish_if_done(b, true, -1);
+    release_batch_resources(b);
+    if (b->graph_exec)
+        (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t ev : {b->ev_k0, b->ev_k1, b->ev_end})
+        if (ev)
+            (void)hipEventDestroy(ev);
+    if (b->dev)
+        (void)hipFree(b->dev);
+    if (b->host)
+        (void)hipHostFree(b->host);
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        st->batches.erase(b);
+    }
+    delete b;
+    return WMI_OK;
+}
+
+int wmi_debug_window(wmi_store *st, const wmi_query *query, const wmi_params *params, uint32_t *nx, uint32_t *ny,
+                     float *ex, float *ey)
+{
+    if (!st || !query || !params || !nx || !ny || !ex || !ey)
+        return fail(WMI_EINVAL, "wmi_debug_window: null argument");
+    if (int rc = validate_params(params))
+        return rc;
+    wmi_query q = *query;
+    q.ext_len = 0;
+    q.ext_side = 0;
+    q.reserved = 0;
+    if (q.len <= params->k)
+        return fail(WMI_EINVAL, "wmi_debug_window: window of %u points has no estimate for k = %u", q.len,
+                    params->k);
+    wmi_params p = *params;
+    p.flags = 0;
+    // run as a one-query batch with the debug pointers set
+    DeviceGuard g(st->device);
+    uint32_t m = q.len;
+    char *dbg = nullptr;
+    HIPCHK(st, hipMalloc(&dbg, 4ull * m * sizeof(uint32_t)));
+    wmi_batch *b = nullptr;
+    // submit normally (runs once), then rerun the main kernel with the debug
+    // pointers set, on the same descriptors and sorted marginals
+    if (int rc = wmi_submit(st, &q, 1, &p, nullptr, &b)) {
+        (void)hipFree(dbg);
+        return rc;
+    }
+    int rc = finish_if_done(b, true, -1);
+    if (rc == WMI_OK) {
+        LaunchArgs a = b->args;
+        a.dbg_nx = reinterpret_cast<uint32_t *>(dbg);
+        a.dbg_ny = a.dbg_nx + m;
+        a.dbg_ex = reinterpret_cast<float *>(a.dbg_ny + m);
+        a.dbg_ey = a.dbg_ex + m;
+        hipStream_t s = b->stream;
+        hipError_t e = launch_clear(a, s);
+        if (e == hipSuccess)
+            e = launch_main(a, b->grid, s);
+        std::vector<uint32_t> h(4ull * m);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), dbg, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = poison(st, e, "wmi_debug_window");
+        } else {
+            std::memcpy(nx, h.data(), m * sizeof(uint32_t));
+            std::memcpy(ny, h.data() + m, m * sizeof(uint32_t));
+            std::memcpy(ex, h.data() + 2ull * m, m * sizeof(float));
+            std::memcpy(ey, h.data() + 3ull * m, m * sizeof(float));
+        }
+    }
+    wmi_batch_destroy(b);
+    (void)hipFree(dbg);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,272 @@
+"""Thin ctypes binding to libwmi.so (include/wmi.h).  Argument marshalling only:
+every step of the computation runs in the library's HIP kernels.
+
+There is no fallback: if libwmi.so is missing or cannot load, every entry
+point raises.  PyTorch is optional and only used to pass device memory and
+streams (``Store.add_series`` accepts a CUDA/HIP tensor; ``stream=`` accepts a
+``torch.cuda.Stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwmi.so")
+
+WMI_OK = 0
+WMI_EINVAL = -1
+WMI_ENOMEM = -2
+WMI_EBUSY = -3
+WMI_ETIMEDOUT = -4
+WMI_EHIP = -5
+WMI_ESTATE = -6
+ERRNAMES = {0: "WMI_OK", -1: "WMI_EINVAL", -2: "WMI_ENOMEM", -3: "WMI_EBUSY", -4: "WMI_ETIMEDOUT",
+            -5: "WMI_EHIP", -6: "WMI_ESTATE"}
+
+F_NOISE = 1
+F_TOO_SHORT = 2
+F_NONPOS_BASE = 4
+F_OFFGRID = 8
+
+STORE_STRICT_GRID = 1
+SUBMIT_NONBLOCKING = 1
+SUBMIT_PLAIN = 2
+MAX_WINDOW = 4096
+MAX_K = 16
+
+QUERY_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("len", "<u4"),
+                        ("ext_len", "<u4"), ("ext_side", "<i4"), ("pad", "<u4")])
+RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f8"),
+                         ("flags", "<u4"), ("pad", "<u4")])
+
+# the symbols include/wmi.h declares
+EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
+           "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
+           "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay",
+           "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table")
+
+
+class WmiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _StoreDesc(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("estimator", ctypes.c_uint32), ("tau", ctypes.c_double),
+                ("tau_normalize", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("windows", ctypes.c_uint64), ("ordered_pairs", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libwmi.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2204_09131_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "wmi_version": ([], ctypes.c_int),
+        "wmi_last_error": ([], ctypes.c_char_p),
+        "wmi_store_create": ([P(_StoreDesc), P(vp)], ctypes.c_int),
+        "wmi_store_destroy": ([vp], ctypes.c_int),
+        "wmi_series_add": ([vp, vp, u64, P(u32)], ctypes.c_int),
+        "wmi_series_add_device": ([vp, vp, u64, vp, P(u32)], ctypes.c_int),
+        "wmi_series_remove": ([vp, u32], ctypes.c_int),
+        "wmi_series_length": ([vp, u32, P(u64)], ctypes.c_int),
+        "wmi_submit": ([vp, vp, u64, P(_Params), vp, P(vp)], ctypes.c_int),
+        "wmi_wait": ([vp, i64], ctypes.c_int),
+        "wmi_done": ([vp], ctypes.c_int),
+        "wmi_read": ([vp, vp], ctypes.c_int),
+        "wmi_batch_replay": ([vp, vp], ctypes.c_int),
+        "wmi_batch_stats_get": ([vp, P(_Stats)], ctypes.c_int),
+        "wmi_batch_destroy": ([vp], ctypes.c_int),
+        "wmi_debug_window": ([vp, vp, P(_Params), vp, vp, vp, vp], ctypes.c_int),
+        "wmi_psi_table": ([u32, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != WMI_OK:
+        raise WmiError(rc, lib().wmi_last_error().decode(errors="replace"))
+
+
+def version() -> tuple:
+    v = lib().wmi_version()
+    return (v >> 16, v & 0xFFFF)
+
+
+def psi_table(n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().wmi_psi_table(n, out.ctypes.data))
+    return out
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _params(k, estimator, tau, tau_normalize, flags) -> _Params:
+    return _Params(int(k), int(estimator), float(tau), int(tau_normalize), int(flags))
+
+
+def as_queries(q) -> np.ndarray:
+    q = np.ascontiguousarray(q)
+    if q.dtype != QUERY_DTYPE:
+        if q.dtype.names and set(QUERY_DTYPE.names) <= set(q.dtype.names) and q.dtype.itemsize == 32:
+            q = q.view(QUERY_DTYPE) if q.dtype.descr == QUERY_DTYPE.descr else q.astype(QUERY_DTYPE)
+        else:
+            raise TypeError("queries must be a structured array with the wmi_query layout")
+    return q
+
+
+class Batch:
+    def __init__(self, store: "Store", handle: int, count: int):
+        self.store = store
+        self.h = ctypes.c_void_p(handle)
+        self.count = count
+
+    def wait(self, timeout_us: int = -1):
+        _check(lib().wmi_wait(self.h, int(timeout_us)))
+
+    def done(self) -> bool:
+        return bool(lib().wmi_done(self.h))
+
+    def read(self) -> np.ndarray:
+        out = np.zeros(self.count, dtype=RESULT_DTYPE)
+        _check(lib().wmi_read(self.h, out.ctypes.data if self.count else None))
+        return out
+
+    def replay(self, stream=None):
+        _check(lib().wmi_batch_replay(self.h, _stream_handle(stream)))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().wmi_batch_stats_get(self.h, ctypes.byref(s)))
+        return {"windows": s.windows, "ordered_pairs": s.ordered_pairs, "launches": s.launches,
+                "device_ms": s.device_ms}
+
+    def destroy(self):
+        if self.h:
+            _check(lib().wmi_batch_destroy(self.h))
+            self.h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            if self.h and self.store.h:
+                lib().wmi_batch_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Store:
+    """A set of resident series on one device."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, strict_grid: bool = False):
+        d = _StoreDesc(int(device), STORE_STRICT_GRID if strict_grid else 0, int(budget_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().wmi_store_create(ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self._borrowed = {}
+
+    def close(self):
+        if self.h:
+            _check(lib().wmi_store_destroy(self.h))
+            self.h = ctypes.c_void_p(None)
+            self._borrowed.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().wmi_store_destroy(self.h)
+        except Exception:
+            pass
+
+    def add_series(self, values, stream=None) -> int:
+        """Host array: copied.  Device tensor (torch, float32, contiguous): borrowed."""
+        sid = ctypes.c_uint32()
+        if hasattr(values, "is_cuda") and values.is_cuda:
+            import torch
+            if values.dtype != torch.float32 or not values.is_contiguous():
+                raise TypeError("device series must be a contiguous float32 tensor")
+            s = _stream_handle(stream if stream is not None else torch.cuda.current_stream(values.device))
+            _check(lib().wmi_series_add_device(self.h, values.data_ptr(), values.numel(), s,
+                                               ctypes.byref(sid)))
+            self._borrowed[sid.value] = values
+        else:
+            v = np.ascontiguousarray(values, dtype=np.float32)
+            _check(lib().wmi_series_add(self.h, v.ctypes.data, v.shape[0], ctypes.byref(sid)))
+        return sid.value
+
+    def remove_series(self, sid: int):
+        _check(lib().wmi_series_remove(self.h, int(sid)))
+        self._borrowed.pop(sid, None)
+
+    def series_length(self, sid: int) -> int:
+        n = ctypes.c_uint64()
+        _check(lib().wmi_series_length(self.h, int(sid), ctypes.byref(n)))
+        return n.value
+
+    def submit(self, queries, k: int = 4, estimator: int = 0, tau: float = 0.0, tau_normalize: int = 0,
+               plain: bool = False, nonblocking: bool = False, stream=None) -> Batch:
+        q = as_queries(queries)
+        flags = (SUBMIT_PLAIN if plain else 0) | (SUBMIT_NONBLOCKING if nonblocking else 0)
+        p = _params(k, estimator, tau, tau_normalize, flags)
+        h = ctypes.c_void_p()
+        _check(lib().wmi_submit(self.h, q.ctypes.data if len(q) else None, len(q), ctypes.byref(p),
+                                _stream_handle(stream), ctypes.byref(h)))
+        return Batch(self, h.value, len(q))
+
+    def evaluate(self, queries, **kw) -> np.ndarray:
+        b = self.submit(queries, **kw)
+        try:
+            return b.read()
+        finally:
+            b.destroy()
+
+    def debug_window(self, a: int, b: int, start: int, length: int, k: int = 4, estimator: int = 0) -> dict:
+        q = np.zeros(1, dtype=QUERY_DTYPE)
+        q["a"], q["b"], q["start"], q["len"] = a, b, start, length
+        nx = np.zeros(length, dtype=np.uint32)
+        ny = np.zeros(length, dtype=np.uint32)
+        ex = np.zeros(length, dtype=np.float32)
+        ey = np.zeros(length, dtype=np.float32)
+        p = _params(k, estimator, 0.0, 0, 0)
+        _check(lib().wmi_debug_window(self.h, q.ctypes.data, ctypes.byref(p), nx.ctypes.data,
+                                      ny.ctypes.data, ex.ctypes.data, ey.ctypes.data))
+        return {"nx": nx, "ny": ny, "eps_x": ex, "eps_y": ey}

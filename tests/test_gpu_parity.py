@@ -1,0 +1,357 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bar: per-point neighbour counts and radii bit-exact (debug export); MI within
+1e-9 absolute; noise flags equal except where the oracle's own margin is
+below 1e-9 (reported).  Batched, plain and replayed forms bit-identical.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_09131_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wmi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_09131_amd import wmi as w
+    w.lib()  # raises if the HIP library is missing
+    return w
+
+
+@pytest.fixture(scope="module")
+def store(wmi):
+    s = wmi.Store(0)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def mi_close(got, ref, fields=("mi_base", "mi_ext", "mi_union")):
+    worst = 0.0
+    for f in fields:
+        a, r = got[f], ref[f]
+        assert np.array_equal(np.isnan(a), np.isnan(r)), f
+        ok = ~np.isnan(r)
+        if ok.any():
+            worst = max(worst, float(np.max(np.abs(a[ok] - r[ok]))))
+    assert worst <= TOL, worst
+    return worst
+
+
+def flags_match(got, ref, tau):
+    diff = np.nonzero(got["flags"] != ref["flags"])[0]
+    for i in diff:
+        r = ref[i]
+        margin = min(abs(r["mi_ext"] - tau), abs(r["mi_union"] - r["mi_base"]), abs(r["mi_base"]))
+        assert margin < TOL, (i, got[i], r)
+    return len(diff)
+
+
+# ---------------------------------------------------------------------------
+# per-point counts, bit-exact
+# ---------------------------------------------------------------------------
+
+COUNT_CASES = [
+    # (m, k, estimator, kind, seed)
+    (5, 4, 0, "grid", 0), (6, 1, 0, "grid", 1), (17, 2, 0, "grid", 2), (64, 4, 0, "normal", 3),
+    (100, 7, 1, "grid", 4), (255, 4, 0, "normal", 5), (256, 16, 0, "grid", 6), (257, 4, 1, "normal", 7),
+    (511, 3, 0, "grid", 8), (512, 4, 0, "normal", 9), (513, 4, 0, "grid", 10), (1000, 5, 1, "normal", 11),
+    (1024, 4, 0, "grid", 12), (2049, 4, 0, "normal", 13), (4096, 4, 0, "normal", 14),
+    (4096, 16, 1, "grid", 15), (3000, 4, 0, "wide", 16), (700, 8, 1, "wide", 17),
+]
+
+
+def make_window(m, kind, seed):
+    if kind == "grid":
+        return synth.grid_points(m, seed, levels=6, scale=1 / 64)
+    if kind == "normal":
+        return synth.bivariate_normal(m, 0.6, seed)
+    if kind == "wide":  # value range too large for 32-bit keys at this m
+        x, y = synth.bivariate_normal(m, 0.6, seed, scale=300.0)
+        return x, y
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("m,k,est,kind,seed", COUNT_CASES)
+def test_debug_counts_bit_exact(store, orc, m, k, est, kind, seed):
+    log(f"counts m={m} k={k} est={est} kind={kind} seed={seed}")
+    x, y = make_window(m, kind, seed)
+    pad = 7  # window starts inside the series
+    xs = np.concatenate([np.zeros(pad, np.float32), x, np.zeros(3, np.float32)])
+    ys = np.concatenate([np.zeros(pad, np.float32), y, np.zeros(3, np.float32)])
+    a = store.add_series(xs)
+    b = store.add_series(ys)
+    try:
+        got = store.debug_window(a, b, pad, m, k=k, estimator=est)
+        ref = orc.window_counts(x, y, k=k, estimator=est)
+        np.testing.assert_array_equal(got["nx"], ref["nx"])
+        np.testing.assert_array_equal(got["ny"], ref["ny"])
+        np.testing.assert_array_equal(got["eps_x"].astype(np.float64), ref["eps_x"])
+        np.testing.assert_array_equal(got["eps_y"].astype(np.float64), ref["eps_y"])
+        q = synth.make_queries(a, b, pad, m)
+        res = store.evaluate(q, k=k, estimator=est)
+        assert abs(res["mi_base"][0] - orc.window_mi(x, y, k, est)) <= TOL
+    finally:
+        store.remove_series(a)
+        store.remove_series(b)
+
+
+# ---------------------------------------------------------------------------
+# full workloads
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1(store):
+    w = synth.config1()
+    ids = [store.add_series(s) for s in w.series]
+    q = w.queries.copy()
+    q["a"], q["b"] = ids
+    return w, q
+
+
+@pytest.fixture(scope="module")
+def cfg2(store):
+    w = synth.config2()
+    ids = [store.add_series(s) for s in w.series]
+    q = w.queries.copy()
+    q["a"], q["b"] = ids
+    return w, q
+
+
+def test_config1_all_windows(store, orc, cfg1):
+    w, q = cfg1
+    log(f"config1: {len(q)} windows")
+    got = store.evaluate(q, k=4)
+    ref = orc.batch(w.series, w.queries, k=4)
+    worst = mi_close(got, ref, ("mi_base",))
+    assert np.array_equal(got["flags"], ref["flags"])
+    log(f"config1 max |dMI| = {worst:.3e}")
+
+
+def test_config1_plain_equals_batched(store, cfg1):
+    w, q = cfg1
+    a = store.evaluate(q, k=4)
+    b = store.evaluate(q, k=4, plain=True)
+    assert np.array_equal(a["mi_base"].view(np.uint64), b["mi_base"].view(np.uint64))
+
+
+def test_config2_all_windows(store, orc, cfg2):
+    w, q = cfg2
+    log(f"config2: {len(q)} windows, {w.ordered_pairs} ordered pairs")
+    got = store.evaluate(q, k=4)
+    ref = orc.batch(w.series, w.queries, k=4)
+    worst = mi_close(got, ref, ("mi_base",))
+    log(f"config2 max |dMI| = {worst:.3e}")
+
+
+def test_config2_replay_bit_identical(store, cfg2):
+    import torch
+    w, q = cfg2
+    b = store.submit(q, k=4)
+    first = b.read().copy()
+    for r in range(3):
+        torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        b.replay()
+        again = b.read()
+        assert np.array_equal(first.view(np.uint8), again.view(np.uint8)), r
+    b.destroy()
+
+
+def test_batching_invariance(store, cfg2):
+    """A window's result is the same alone, in the full batch and permuted."""
+    w, q = cfg2
+    full = store.evaluate(q, k=4)
+    rng = np.random.Generator(np.random.PCG64(5))
+    perm = rng.permutation(len(q))
+    permuted = store.evaluate(q[perm], k=4)
+    assert np.array_equal(full["mi_base"][perm].view(np.uint64), permuted["mi_base"].view(np.uint64))
+    for i in rng.choice(len(q), 12, replace=False):
+        alone = store.evaluate(q[i:i + 1], k=4)
+        assert alone["mi_base"][0].tobytes() == full["mi_base"][i].tobytes()
+
+
+def test_symmetry_bit_exact(store, cfg2):
+    w, q = cfg2
+    sub = q[::37].copy()
+    swapped = sub.copy()
+    swapped["a"], swapped["b"] = sub["b"], sub["a"]
+    a = store.evaluate(sub, k=4)
+    b = store.evaluate(swapped, k=4)
+    assert np.array_equal(a["mi_base"].view(np.uint64), b["mi_base"].view(np.uint64))
+
+
+@pytest.mark.parametrize("k,est", [(1, 0), (3, 1), (8, 0), (16, 0)])
+def test_other_k_and_estimator(store, orc, cfg2, k, est):
+    w, q = cfg2
+    sub = np.concatenate([q[::301], q[-121::7]])
+    log(f"k={k} est={est}: {len(sub)} windows")
+    got = store.evaluate(sub, k=k, estimator=est)
+    qq = sub.copy()
+    qq["a"], qq["b"] = 0, 1
+    ref = orc.batch(w.series, qq, k=k, estimator=est)
+    mi_close(got, ref, ("mi_base",))
+
+
+def test_noise_triples_config3_sample(store, orc):
+    w = synth.config3(pairs=[(0, 33), (5, 40), (12, 20), (50, 60)])
+    ids = [store.add_series(s) for s in w.series]
+    q = w.queries.copy()
+    q["a"] = np.array(ids, dtype=np.uint32)[q["a"]]
+    q["b"] = np.array(ids, dtype=np.uint32)[q["b"]]
+    sel = np.arange(0, len(q), 5)
+    log(f"config3 sample: {len(sel)} triples, tau={w.tau:.4f}")
+    got = store.evaluate(q[sel], k=4, tau=w.tau)
+    ref = orc.batch(w.series, w.queries[sel], k=4, tau=w.tau)
+    mi_close(got, ref)
+    nd = flags_match(got, ref, w.tau)
+    log(f"config3 flags differing inside the 1e-9 margin: {nd}; noise flags set: "
+        f"{int(np.count_nonzero(got['flags'] & 1))}")
+    for i in ids:
+        store.remove_series(i)
+
+
+def test_left_and_right_triples_and_short_windows(store, orc):
+    x, y = synth.relation("quadratic", 3000, 21)
+    a, b = store.add_series(x), store.add_series(y)
+    q = np.concatenate([
+        synth.make_queries(a, b, [100, 700, 1500], 300, 60, +1),
+        synth.make_queries(a, b, [400, 900, 2000], 200, 100, -1),
+        synth.make_queries(a, b, [10, 20], 4, 0, 0),            # m <= k: NaN, TOO_SHORT
+        synth.make_queries(a, b, [30], 5, 0, 0),                # m = k + 1
+        synth.make_queries(a, b, [50], 100, 3, +1),             # short extension
+        synth.make_queries(a, b, [60], 3, 100, -1),             # short base
+        synth.make_queries(a, b, [0], 4096 - 8, 8, +1),         # largest union
+    ])
+    got = store.evaluate(q, k=4, tau=0.05)
+    qq = q.copy()
+    qq["a"], qq["b"] = 0, 1
+    ref = orc.batch([x, y], qq, k=4, tau=0.05)
+    mi_close(got, ref)
+    flags_match(got, ref, 0.05)
+    assert got["flags"][6] & 2 and np.isnan(got["mi_base"][6])
+    store.remove_series(a)
+    store.remove_series(b)
+
+
+def test_tau_normalize(store, orc):
+    x, y = synth.relation("sine", 2000, 3)
+    a, b = store.add_series(x), store.add_series(y)
+    q = synth.make_queries(a, b, np.arange(0, 1500, 50), 256, 16, +1)
+    got = store.evaluate(q, k=4, tau=0.1, tau_normalize=1)
+    qq = q.copy()
+    qq["a"], qq["b"] = 0, 1
+    ref = orc.batch([x, y], qq, k=4, tau=0.1, tau_normalize=1)
+    mi_close(got, ref)
+    flags_match(got, ref, 0.1 * math.log(16))
+    store.remove_series(a)
+    store.remove_series(b)
+
+
+def test_offgrid_flag_and_device_series(store, orc):
+    import torch
+    x, y = synth.relation("linear", 500, 8)
+    xo = x.copy()
+    xo[17] += np.float32(1e-4)  # off the grid
+    a = store.add_series(xo)
+    bt = torch.from_numpy(y).to("cuda")
+    b = store.add_series(bt)
+    q = synth.make_queries(a, b, [0, 100, 200], 64)
+    got = store.evaluate(q, k=4)
+    assert got["flags"][0] & 8 and not (got["flags"][1] & 8) and not (got["flags"][2] & 8)
+    qq = q.copy()
+    qq["a"], qq["b"] = 0, 1
+    ref = orc.batch([x, y], qq[1:], k=4)
+    mi_close(got[1:], ref, ("mi_base",))
+    store.remove_series(a)
+    store.remove_series(b)
+
+
+# ---------------------------------------------------------------------------
+# error contract
+# ---------------------------------------------------------------------------
+
+def test_errors(wmi, store):
+    x, y = synth.relation("linear", 300, 1)
+    a, b = store.add_series(x), store.add_series(y)
+    bad = [
+        synth.make_queries(a, 999, 0, 64),                 # unknown series
+        synth.make_queries(a, b, 250, 64),                 # past the end
+        synth.make_queries(a, b, 0, 0),                    # empty window
+        synth.make_queries(a, b, 10, 64, 8, -1),           # left extension before start
+        synth.make_queries(a, b, 0, 100, 0, +1),           # empty extension
+        synth.make_queries(a, b, 0, 64, 8, 2),             # bad side
+    ]
+    for q in bad:
+        with pytest.raises(wmi.WmiError) as e:
+            store.submit(q, k=4)
+        assert e.value.code == wmi.WMI_EINVAL
+    q = synth.make_queries(a, b, 0, 64)
+    for kw in ({"k": 0}, {"k": 17}, {"estimator": 2}):
+        with pytest.raises(wmi.WmiError) as e:
+            store.submit(q, **kw)
+        assert e.value.code == wmi.WMI_EINVAL
+    q2 = q.copy()
+    q2["pad"] = 1
+    with pytest.raises(wmi.WmiError):
+        store.submit(q2, k=4)
+    with pytest.raises(wmi.WmiError) as e:
+        store.add_series(np.array([1.0, np.nan], np.float32))
+    assert e.value.code == wmi.WMI_EINVAL
+    # a series read by an unfinished batch cannot be removed
+    big = synth.make_queries(a, b, np.zeros(2000, np.uint64), 256)
+    bt = store.submit(big, k=4)
+    try:
+        store.remove_series(a)
+        removed = True
+    except wmi.WmiError as e:
+        assert e.code == wmi.WMI_EBUSY
+        removed = False
+    bt.read()
+    bt.destroy()
+    if not removed:
+        store.remove_series(a)
+    store.remove_series(b)
+    # empty batch
+    assert len(store.evaluate(np.zeros(0, dtype=wmi.QUERY_DTYPE), k=4)) == 0
+
+
+def test_budget(wmi):
+    with wmi.Store(0, budget_bytes=1 << 20) as st:
+        x, y = synth.relation("linear", 5000, 1)
+        a, b = st.add_series(x), st.add_series(y)
+        q = synth.make_queries(a, b, np.arange(0, 4000, 1), 512)
+        with pytest.raises(wmi.WmiError) as e:
+            st.submit(q, k=4)
+        assert e.value.code == wmi.WMI_ENOMEM
+        small = synth.make_queries(a, b, np.arange(0, 300, 1), 256)  # ~0.65 MiB: two do not fit
+        b1 = st.submit(small, k=4)
+        try:
+            b2 = st.submit(small, k=4, nonblocking=True)
+            b2.destroy()
+        except wmi.WmiError as e:
+            assert e.code == wmi.WMI_EBUSY
+        b1.read()
+        b1.destroy()
+        b3 = st.submit(small, k=4, nonblocking=True)  # fits once b1 finished
+        b3.read()
+        b3.destroy()
