@@ -1,0 +1,208 @@
+"""Benchmark: windowed KSG MI over the multi-scale workload on one MI355X.
+
+Workload (one step): one pair of float32 series, n = 65,536, on the 2^-12
+grid, segments of linear / quadratic / sine / independent links with lengths
+uniform in [256, 4096]; windows w in {32, 64, ..., 4096} with stride w/8, all
+8 scales in one batch (32,584 windows, 4,117,467,936 ordered point pairs),
+k = 4, Eq. (2) estimator.  Series are resident in HBM before timing starts.
+
+A step = one run of the batch: descriptor upload, clear, prep kernel (sorted
+marginals), persistent main kernel (neighbours, counts, digamma sums, MI),
+result download.  Steps are enqueued back to back on one stream (pipelined),
+with HIP events around each kernel; `value` is windows / (wall time / step).
+
+Also reported: the same steps as HIP-graph launches, the plain form (one
+prep + one main launch per window), end-to-end query latency (fresh submit ->
+results on host), the roofline of the main kernel and the CPU oracle on the
+host's cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "window-MI evals/s and distance ops/s (% FP32 VALU peak); p50/p99 query latency"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test, 2 x (difference + compare)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(workload, budget_s: float = 20.0) -> dict:
+    """The oracle as it stands, on every host core, over a bounded sample."""
+    import oracle
+    orc = oracle.load()
+    cores = orc.threads(len(os.sched_getaffinity(0)))
+    q = workload.queries
+    # a strided sample holding every scale; grown until it takes a few seconds
+    step = 64
+    t_used = 0.0
+    while True:
+        sub = q[::step]
+        t0 = time.perf_counter()
+        orc.batch(workload.series, sub, k=workload.k)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        if dt > 3.0 or step == 1 or t_used > budget_s:
+            break
+        step = max(1, step // 4)
+    return {"value": len(sub) / dt, "unit": "window-MI evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sub)} of {len(q)} windows (every {step}-th, all scales), {dt:.2f} s",
+            "pairs_per_s": float(np.sum(sub['len'].astype(np.float64) * (sub['len'] - 1.0))) / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--latency-samples", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(windows are independent; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_09131_amd import synth, wmi
+
+    if not os.path.exists(wmi.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    w = synth.config2()
+    n_win = len(w.queries)
+    pairs = w.ordered_pairs
+    log(f"workload {w.name}: {n_win} windows, {pairs} ordered pairs")
+
+    st = wmi.Store(0)
+    ids = [st.add_series(s) for s in w.series]
+    q = w.queries.copy()
+    q["a"], q["b"] = ids
+    b = st.submit(q, k=w.k)
+    first = b.read()
+    assert np.all(np.isfinite(first["mi_base"]))
+
+    # ---- timed region: pipelined direct runs with per-kernel events --------
+    for _ in range(args.warmup):
+        b.replay(direct=True)
+    b.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay(direct=True)
+    b.wait()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = b.timing()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = n_win / (ms_step / 1e3)
+    again = b.read()
+    assert np.array_equal(first.view(np.uint8), again.view(np.uint8)), "replay changed results"
+    log(f"direct: {ms_step:.3f} ms/step, main kernel {tim['main_ms']:.3f} ms, prep {tim['prep_ms']:.3f} ms")
+
+    # ---- the same steps as graph launches -----------------------------------
+    b.replay()
+    b.wait()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay()
+    b.wait()
+    torch.cuda.synchronize()
+    g_ms = (time.perf_counter() - g0) / args.steps * 1e3
+    log(f"graph: {g_ms:.3f} ms/step")
+    b.destroy()
+
+    # ---- query latency: fresh submit -> results on the host -------------------
+    lat = []
+    for _ in range(args.latency_samples):
+        s0 = time.perf_counter()
+        r = st.evaluate(q, k=w.k)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    lat = np.array(lat)
+    log(f"query latency p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms")
+
+    # ---- plain form: one prep + one main launch per window ------------------
+    plain = None
+    if not args.no_plain:
+        bp = st.submit(q, k=w.k, plain=True)
+        bp.wait()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        bp.replay()
+        bp.wait()
+        p_ms = (time.perf_counter() - p0) * 1e3
+        pt = bp.timing()
+        assert np.array_equal(bp.read()["mi_base"].view(np.uint64), first["mi_base"].view(np.uint64))
+        bp.destroy()
+        plain = {"ms_per_step": p_ms, "value": n_win / (p_ms / 1e3), "device_ms": pt["total_ms"],
+                 "launches": 1 + 2 * n_win}
+        log(f"plain: {p_ms:.1f} ms/step")
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    st.close()
+
+    achieved = pairs * OPS_PER_PAIR / (tim["main_ms"] / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "window-MI evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "windows": n_win, "ordered_pairs": pairs, "k": w.k,
+                   "estimator": "eq2 (per-dimension radii)", "scales": list(synth.CFG2_SCALES),
+                   "series_len": len(w.series[0])},
+        "pairs_per_s": pairs / (ms_step / 1e3),
+        "distance_ops_frac_valu_peak": pairs * OPS_PER_PAIR / (ms_step / 1e3) / 1e12 / VALU_PEAK_TOPS,
+        "device_ms_per_step": tim["total_ms"],
+        "graph_ms_per_step": g_ms,
+        "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "samples": int(len(lat)), "what": "fresh submit of the whole batch to results on host"},
+        "kernels_ms": {"main": tim["main_ms"], "prep": tim["prep_ms"], "runs": tim["runs"]},
+        "roofline": {"bound": "alu", "kernel": "main_kernel<4>", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None,
+                     "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs},
+        "plain_gpu": plain,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,14 +185,31 @@ int wmi_done(wmi_batch *batch);
 /* Wait for the batch, then copy its `count` results to host_out. */
 int wmi_read(wmi_batch *batch, wmi_result *host_out);
 
+/* ---- replay flags ------------------------------------------------------------ */
+#define WMI_REPLAY_DIRECT 1u /* enqueue kernel by kernel (per-kernel timing), no graph */
+
 /*
  * Run the batch's work again, unchanged, on `stream` (NULL: the stream it was
- * submitted on): descriptor upload, kernels and result download are captured
- * once into a HIP graph and replayed.  Results are overwritten with the same
- * values.  The batch must be finished; WMI_SUBMIT_PLAIN batches are replayed
- * launch by launch without a graph.
+ * submitted on): descriptor upload, kernels and result download.  By default
+ * the sequence is captured once into a HIP graph and the graph is launched;
+ * WMI_REPLAY_DIRECT enqueues the kernels one by one with events around each.
+ * Runs may be pipelined: a replay does not wait for earlier runs, which are
+ * ordered before it on the same stream; results are overwritten with the same
+ * values.  WMI_SUBMIT_PLAIN batches always replay launch by launch.
  */
-int wmi_batch_replay(wmi_batch *batch, void *stream);
+int wmi_batch_replay(wmi_batch *batch, void *stream, uint32_t flags);
+
+/* Average event timings over the most recent runs of a batch (up to 16);
+ * waits for the batch.  mode: 0 direct, 1 graph, 2 plain, -1 mixed. */
+typedef struct {
+    uint32_t runs;
+    int32_t mode;
+    double total_ms; /* upload + kernels + download                               */
+    double prep_ms;  /* prep (sorted marginals) kernel; NaN unless mode 0          */
+    double main_ms;  /* main (neighbours, counts, digamma) kernel; NaN unless mode 0 */
+} wmi_timing;
+
+int wmi_batch_timing(wmi_batch *batch, wmi_timing *out);
 
 /* Counters and device time of a finished batch (of its last run). */
 int wmi_batch_stats_get(wmi_batch *batch, wmi_batch_stats *out);

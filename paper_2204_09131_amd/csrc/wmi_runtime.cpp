@@ -108,6 +108,13 @@ struct wmi_store {
     std::set<wmi_batch *> batches;
 };
 
+// Events of one run: start, prep start, main start, main end, end.
+struct RunEvents {
+    hipEvent_t s0 = nullptr, p0 = nullptr, m0 = nullptr, m1 = nullptr, s1 = nullptr;
+    int mode = 0;  // 0 direct (per-kernel events valid), 1 graph, 2 plain
+};
+constexpr int kSlots = 16;  // runs whose timings are kept
+
 struct wmi_batch {
     wmi_store *st = nullptr;
     uint64_t count = 0;
@@ -116,7 +123,6 @@ struct wmi_batch {
     // device buffer and its layout
     char *dev = nullptr;
     size_t dev_bytes = 0;
-    bool budget_held = false;
     // pinned host buffer: descriptors followed by results
     char *host = nullptr;
     size_t host_bytes = 0;
@@ -126,15 +132,18 @@ struct wmi_batch {
     std::vector<uint32_t> win_first_item;  // plain form: first item of each window
     Result *h_res = nullptr;
     Result *d_res = nullptr;
-    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_end = nullptr;
+    RunEvents slot[kSlots];
+    hipEvent_t ev_end = nullptr;  // recorded after the completion callback of the latest run
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint32_t> series_used;
     wmi_batch_stats stats{};
-    std::atomic<int> complete{0};  // set by the stream callback after the download
-    bool enqueued = false;         // the last run was fully enqueued (callback + event)
-    bool finished = false;         // completion observed by the owner (stats read)
-    bool series_released = false;
+    // run bookkeeping, guarded by the store mutex: runs may be pipelined on a
+    // stream; budget and series pins are held while any run is pending
+    uint64_t runs_enq = 0;
+    uint64_t runs_done = 0;
+    bool held = false;
+    bool enqueue_failed = false;
 };
 
 namespace {
@@ -168,31 +177,41 @@ bool value_on_grid(float v)
     return std::isfinite(s) && s == std::nearbyint(s) && std::fabs(s) <= 8388607.0;
 }
 
-// Release the series pins and the memory budget of a finished batch.
-void release_batch_resources(wmi_batch *b)
+// Take the budget and series pins for a pending run (store mutex held).
+void hold_locked(wmi_batch *b)
 {
     wmi_store *st = b->st;
-    std::lock_guard<std::mutex> lk(st->mu);
-    if (!b->series_released) {
-        for (uint32_t id : b->series_used)
-            if (id < st->series.size() && st->series[id].busy)
-                st->series[id].busy--;
-        b->series_released = true;
-    }
-    if (b->budget_held) {
-        st->inflight -= b->dev_bytes;
-        b->budget_held = false;
-    }
+    if (b->held)
+        return;
+    for (uint32_t id : b->series_used)
+        st->series[id].busy++;
+    st->inflight += b->dev_bytes;
+    b->held = true;
+}
+
+// Give them back once no run is pending (store mutex held).
+void release_locked(wmi_batch *b)
+{
+    wmi_store *st = b->st;
+    if (!b->held)
+        return;
+    for (uint32_t id : b->series_used)
+        if (id < st->series.size() && st->series[id].busy)
+            st->series[id].busy--;
+    st->inflight -= b->dev_bytes;
+    b->held = false;
     st->cv.notify_all();
 }
 
-int enqueue_work(wmi_batch *b, hipStream_t s)
+int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
 {
     wmi_store *st = b->st;
     const LaunchArgs &a = b->args;
     if (b->desc_bytes)
         HIPCHK(st, hipMemcpyAsync(b->dev, b->host, b->desc_bytes, hipMemcpyHostToDevice, s));
     HIPCHK(st, launch_clear(a, s));
+    if (ev)
+        HIPCHK(st, hipEventRecord(ev->p0, s));
     if (b->params.flags & WMI_SUBMIT_PLAIN) {
         // baseline form: every window is its own prep launch and main launch
         for (uint32_t w = 0; w < a.n_win; ++w) {
@@ -204,9 +223,17 @@ int enqueue_work(wmi_batch *b, hipStream_t s)
             aw.persistent = 0;
             HIPCHK(st, launch_main(aw, aw.n_items, s));
         }
+        if (ev) {
+            HIPCHK(st, hipEventRecord(ev->m0, s));
+            HIPCHK(st, hipEventRecord(ev->m1, s));
+        }
     } else {
         HIPCHK(st, launch_prep(a, a.n_win, s));
+        if (ev)
+            HIPCHK(st, hipEventRecord(ev->m0, s));
         HIPCHK(st, launch_main(a, b->grid, s));
+        if (ev)
+            HIPCHK(st, hipEventRecord(ev->m1, s));
     }
     if (b->count)
         HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->count * sizeof(Result), hipMemcpyDeviceToHost, s));
@@ -214,50 +241,91 @@ int enqueue_work(wmi_batch *b, hipStream_t s)
 }
 
 // Runs on a HIP runtime thread once everything enqueued before it on the
-// stream has finished: releases the batch's memory budget and series pins.
-void on_batch_complete(void *user)
+// stream has finished; the last pending run releases budget and pins.
+void on_run_complete(void *user)
 {
     wmi_batch *b = static_cast<wmi_batch *>(user);
-    release_batch_resources(b);
-    b->complete.store(1, std::memory_order_release);
+    std::lock_guard<std::mutex> lk(b->st->mu);
+    b->runs_done++;
+    if (b->runs_done == b->runs_enq)
+        release_locked(b);
 }
 
-int run_batch(wmi_batch *b, hipStream_t s)
+int create_slot(wmi_store *st, RunEvents &e)
+{
+    if (e.s0)
+        return WMI_OK;
+    for (hipEvent_t *p : {&e.s0, &e.p0, &e.m0, &e.m1, &e.s1})
+        HIPCHK(st, hipEventCreate(p));
+    return WMI_OK;
+}
+
+// Enqueue one run.  mode: 0 direct with per-kernel events, 1 graph launch.
+int run_batch(wmi_batch *b, hipStream_t s, int mode)
 {
     wmi_store *st = b->st;
-    b->complete.store(0, std::memory_order_relaxed);
-    b->enqueued = false;
-    HIPCHK(st, hipEventRecord(b->ev_k0, s));
-    if (b->graph_exec) {
-        HIPCHK(st, hipGraphLaunch(b->graph_exec, s));
-    } else {
-        int rc = enqueue_work(b, s);
-        if (rc)
-            return rc;
+    uint64_t run;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        for (uint32_t id : b->series_used)
+            if (id >= st->series.size() || !st->series[id].live)
+                return fail(WMI_ESTATE, "series %u of the batch was removed", id);
+        hold_locked(b);
+        run = b->runs_enq++;
     }
-    HIPCHK(st, hipEventRecord(b->ev_k1, s));
-    HIPCHK(st, hipLaunchHostFunc(s, on_batch_complete, b));
-    HIPCHK(st, hipEventRecord(b->ev_end, s));
-    b->enqueued = true;
-    b->finished = false;
+    RunEvents &ev = b->slot[run % kSlots];
+    int rc = create_slot(st, ev);
+    if (rc == WMI_OK) {
+        ev.mode = (b->params.flags & WMI_SUBMIT_PLAIN) ? 2 : mode;
+        hipError_t e = hipEventRecord(ev.s0, s);
+        if (e != hipSuccess)
+            rc = poison(st, e, "hipEventRecord");
+        else if (mode == 1)
+            rc = (e = hipGraphLaunch(b->graph_exec, s)) == hipSuccess ? WMI_OK : poison(st, e, "hipGraphLaunch");
+        else
+            rc = enqueue_work(b, s, &ev);
+        if (rc == WMI_OK && (e = hipEventRecord(ev.s1, s)) != hipSuccess)
+            rc = poison(st, e, "hipEventRecord");
+        if (rc == WMI_OK && (e = hipLaunchHostFunc(s, on_run_complete, b)) != hipSuccess)
+            rc = poison(st, e, "hipLaunchHostFunc");
+        if (rc == WMI_OK && (e = hipEventRecord(b->ev_end, s)) != hipSuccess)
+            rc = poison(st, e, "hipEventRecord");
+    }
+    if (rc != WMI_OK) {
+        // the completion callback of this run is not enqueued: undo its count
+        std::lock_guard<std::mutex> lk(st->mu);
+        b->runs_enq--;
+        b->enqueue_failed = true;
+        if (b->runs_done == b->runs_enq)
+            release_locked(b);
+        return rc;
+    }
     b->stats.launches = (b->params.flags & WMI_SUBMIT_PLAIN) ? 1 + 2ull * b->args.n_win : 3;
     return WMI_OK;
 }
 
+bool runs_pending(wmi_batch *b)
+{
+    std::lock_guard<std::mutex> lk(b->st->mu);
+    return b->runs_done != b->runs_enq;
+}
+
+// Wait (or poll) until every enqueued run of the batch has completed.
 int finish_if_done(wmi_batch *b, bool block, int64_t timeout_us)
 {
-    if (b->finished)
-        return WMI_OK;
     wmi_store *st = b->st;
-    if (!b->enqueued)
-        return fail(WMI_ESTATE, "batch was not fully enqueued");
     auto t0 = std::chrono::steady_clock::now();
     for (;;) {
-        hipError_t e = hipEventQuery(b->ev_end);
-        if (e == hipSuccess && b->complete.load(std::memory_order_acquire))
+        if (!runs_pending(b))
             break;
+        hipError_t e = hipEventQuery(b->ev_end);
         if (e != hipSuccess && e != hipErrorNotReady)
             return poison(st, e, "hipEventQuery");
+        {
+            std::lock_guard<std::mutex> lk(st->mu);
+            if (st->poisoned)
+                return fail(WMI_EHIP, "store poisoned: %s", st->poison_msg.c_str());
+        }
         if (!block)
             return WMI_ETIMEDOUT;
         if (timeout_us >= 0) {
@@ -267,10 +335,12 @@ int finish_if_done(wmi_batch *b, bool block, int64_t timeout_us)
         }
         std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, b->ev_k0, b->ev_k1) == hipSuccess)
-        b->stats.device_ms = ms;
-    b->finished = true;
+    if (b->runs_enq) {
+        const RunEvents &ev = b->slot[(b->runs_enq - 1) % kSlots];
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.s0, ev.s1) == hipSuccess)
+            b->stats.device_ms = ms;
+    }
     return WMI_OK;
 }
 
@@ -615,31 +685,34 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
             // running batches release their budget from the stream callback
             st->cv.wait(lk, [&] { return st->inflight + dev_bytes <= st->budget; });
         }
-        for (uint32_t id : used) {
+        for (uint32_t id : used)
             if (id >= st->series.size() || !st->series[id].live)
                 return fail(WMI_EINVAL, "wmi_submit: series %u removed during submit", id);
-            st->series[id].busy++;
-        }
-        st->inflight += dev_bytes;
     }
-
     wmi_batch *b = new wmi_batch();
     b->st = st;
     b->count = count;
     b->params = *p;
     b->stream = stream ? (hipStream_t)stream : st->stream;
     b->series_used = used;
-    b->budget_held = true;
     b->dev_bytes = dev_bytes;
     b->desc_bytes = desc_bytes;
     b->stats.windows = n_win;
     b->stats.ordered_pairs = pairs;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        hold_locked(b);  // reserve budget and pins until the batch's runs complete
+    }
 
     auto bail = [&](hipError_t e, const char *what) {
         int rc = poison(st, e, what);
-        release_batch_resources(b);
+        {
+            std::lock_guard<std::mutex> lk(st->mu);
+            release_locked(b);
+        }
         if (b->dev) (void)hipFree(b->dev);
         if (b->host) (void)hipHostFree(b->host);
+        if (b->ev_end) (void)hipEventDestroy(b->ev_end);
         delete b;
         return rc;
     };
@@ -650,11 +723,9 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, A), hipHostMallocDefault);
     if (e != hipSuccess)
         return bail(e, "hipHostMalloc(batch)");
-    for (hipEvent_t *ev : {&b->ev_k0, &b->ev_k1, &b->ev_end}) {
-        e = hipEventCreate(ev);
-        if (e != hipSuccess)
-            return bail(e, "hipEventCreate");
-    }
+    e = hipEventCreate(&b->ev_end);
+    if (e != hipSuccess)
+        return bail(e, "hipEventCreate");
 
     // ---- descriptors --------------------------------------------------------
     WinDesc *hw = reinterpret_cast<WinDesc *>(b->host + o_win);
@@ -745,7 +816,7 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         std::lock_guard<std::mutex> lk(st->mu);
         st->batches.insert(b);
     }
-    int rc = run_batch(b, b->stream);
+    int rc = run_batch(b, b->stream, 0);
     if (rc) {
         (void)hipStreamSynchronize(b->stream);
         wmi_batch_destroy(b);
@@ -783,43 +854,67 @@ int wmi_read(wmi_batch *b, wmi_result *out)
     return WMI_OK;
 }
 
-int wmi_batch_replay(wmi_batch *b, void *stream)
+int wmi_batch_replay(wmi_batch *b, void *stream, uint32_t flags)
 {
     if (!b)
         return fail(WMI_EINVAL, "wmi_batch_replay: null batch");
+    if (flags & ~WMI_REPLAY_DIRECT)
+        return fail(WMI_EINVAL, "wmi_batch_replay: unknown flags 0x%x", flags);
     wmi_store *st = b->st;
     DeviceGuard g(st->device);
-    if (int rc = finish_if_done(b, true, -1))
-        return rc;
     if (int rc = check_poison(st))
         return rc;
     hipStream_t s = stream ? (hipStream_t)stream : b->stream;
-    {
-        // a replay holds the batch's budget and series pins again
-        std::lock_guard<std::mutex> lk(st->mu);
-        for (uint32_t id : b->series_used) {
-            if (id >= st->series.size() || !st->series[id].live)
-                return fail(WMI_ESTATE, "wmi_batch_replay: series %u was removed", id);
-        }
-        for (uint32_t id : b->series_used)
-            st->series[id].busy++;
-        b->series_released = false;
-        st->inflight += b->dev_bytes;
-        b->budget_held = true;
-    }
-    if (!(b->params.flags & WMI_SUBMIT_PLAIN) && !b->graph_exec) {
+    const bool graph = !(flags & WMI_REPLAY_DIRECT) && !(b->params.flags & WMI_SUBMIT_PLAIN);
+    if (graph && !b->graph_exec) {
         HIPCHK(st, hipStreamBeginCapture(st->capture_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_work(b, st->capture_stream);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(st->capture_stream, &graph);
+        int rc = enqueue_work(b, st->capture_stream, nullptr);
+        hipGraph_t graph_h = nullptr;
+        hipError_t e = hipStreamEndCapture(st->capture_stream, &graph_h);
         if (rc)
             return rc;
         if (e != hipSuccess)
             return poison(st, e, "hipStreamEndCapture");
-        b->graph = graph;
-        HIPCHK(st, hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0));
+        b->graph = graph_h;
+        HIPCHK(st, hipGraphInstantiate(&b->graph_exec, graph_h, nullptr, nullptr, 0));
     }
-    return run_batch(b, s);
+    return run_batch(b, s, graph ? 1 : 0);
+}
+
+int wmi_batch_timing(wmi_batch *b, wmi_timing *out)
+{
+    if (!b || !out)
+        return fail(WMI_EINVAL, "wmi_batch_timing: null argument");
+    DeviceGuard g(b->st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    std::memset(out, 0, sizeof *out);
+    const double nan = std::nan("");
+    uint64_t n = std::min<uint64_t>(b->runs_enq, kSlots);
+    double tot = 0, prep = 0, mainv = 0;
+    int mode = -1;
+    bool mixed = false;
+    for (uint64_t r = b->runs_enq - n; r < b->runs_enq; ++r) {
+        const RunEvents &ev = b->slot[r % kSlots];
+        float a = 0, p = 0, m = 0;
+        HIPCHK(b->st, hipEventElapsedTime(&a, ev.s0, ev.s1));
+        tot += a;
+        if (ev.mode == 0) {
+            HIPCHK(b->st, hipEventElapsedTime(&p, ev.p0, ev.m0));
+            HIPCHK(b->st, hipEventElapsedTime(&m, ev.m0, ev.m1));
+            prep += p;
+            mainv += m;
+        }
+        if (mode >= 0 && mode != ev.mode)
+            mixed = true;
+        mode = ev.mode;
+    }
+    out->runs = (uint32_t)n;
+    out->mode = mixed ? -1 : mode;
+    out->total_ms = n ? tot / (double)n : nan;
+    out->prep_ms = (n && mode == 0 && !mixed) ? prep / (double)n : nan;
+    out->main_ms = (n && mode == 0 && !mixed) ? mainv / (double)n : nan;
+    return WMI_OK;
 }
 
 int wmi_batch_stats_get(wmi_batch *b, wmi_batch_stats *out)
@@ -839,24 +934,30 @@ int wmi_batch_destroy(wmi_batch *b)
         return WMI_OK;
     wmi_store *st = b->st;
     DeviceGuard g(st->device);
-    (void)hipEventSynchronize(b->ev_end);
-    (void)finish_if_done(b, true, -1);
-    release_batch_resources(b);
+    int rc = finish_if_done(b, true, -1);
+    if (rc != WMI_OK) {
+        // a HIP error left runs pending; wait for the stream before freeing
+        (void)hipStreamSynchronize(b->stream);
+    }
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        release_locked(b);
+        st->batches.erase(b);
+    }
     if (b->graph_exec)
         (void)hipGraphExecDestroy(b->graph_exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    for (hipEvent_t ev : {b->ev_k0, b->ev_k1, b->ev_end})
-        if (ev)
-            (void)hipEventDestroy(ev);
+    for (RunEvents &ev : b->slot)
+        for (hipEvent_t e : {ev.s0, ev.p0, ev.m0, ev.m1, ev.s1})
+            if (e)
+                (void)hipEventDestroy(e);
+    if (b->ev_end)
+        (void)hipEventDestroy(b->ev_end);
     if (b->dev)
         (void)hipFree(b->dev);
     if (b->host)
         (void)hipHostFree(b->host);
-    {
-        std::lock_guard<std::mutex> lk(st->mu);
-        st->batches.erase(b);
-    }
     delete b;
     return WMI_OK;
 }

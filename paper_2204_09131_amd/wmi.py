@@ -45,8 +45,9 @@ RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f
 # the symbols include/wmi.h declares
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
-           "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay",
+           "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
            "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table")
+REPLAY_DIRECT = 1
 
 
 class WmiError(RuntimeError):
@@ -62,6 +63,11 @@ class _StoreDesc(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("estimator", ctypes.c_uint32), ("tau", ctypes.c_double),
                 ("tau_normalize", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_uint32), ("mode", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("prep_ms", ctypes.c_double), ("main_ms", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -96,7 +102,8 @@ def lib():
         "wmi_wait": ([vp, i64], ctypes.c_int),
         "wmi_done": ([vp], ctypes.c_int),
         "wmi_read": ([vp, vp], ctypes.c_int),
-        "wmi_batch_replay": ([vp, vp], ctypes.c_int),
+        "wmi_batch_replay": ([vp, vp, u32], ctypes.c_int),
+        "wmi_batch_timing": ([vp, P(_Timing)], ctypes.c_int),
         "wmi_batch_stats_get": ([vp, P(_Stats)], ctypes.c_int),
         "wmi_batch_destroy": ([vp], ctypes.c_int),
         "wmi_debug_window": ([vp, vp, P(_Params), vp, vp, vp, vp], ctypes.c_int),
@@ -165,8 +172,15 @@ class Batch:
         _check(lib().wmi_read(self.h, out.ctypes.data if self.count else None))
         return out
 
-    def replay(self, stream=None):
-        _check(lib().wmi_batch_replay(self.h, _stream_handle(stream)))
+    def replay(self, stream=None, direct: bool = False):
+        """Enqueue another run (graph launch, or kernel by kernel if direct)."""
+        _check(lib().wmi_batch_replay(self.h, _stream_handle(stream), REPLAY_DIRECT if direct else 0))
+
+    def timing(self) -> dict:
+        t = _Timing()
+        _check(lib().wmi_batch_timing(self.h, ctypes.byref(t)))
+        return {"runs": t.runs, "mode": t.mode, "total_ms": t.total_ms, "prep_ms": t.prep_ms,
+                "main_ms": t.main_ms}
 
     def stats(self) -> dict:
         s = _Stats()

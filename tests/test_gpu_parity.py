@@ -239,7 +239,7 @@ def test_left_and_right_triples_and_short_windows(store, orc):
         synth.make_queries(a, b, [10, 20], 4, 0, 0),            # m <= k: NaN, TOO_SHORT
         synth.make_queries(a, b, [30], 5, 0, 0),                # m = k + 1
         synth.make_queries(a, b, [50], 100, 3, +1),             # short extension
-        synth.make_queries(a, b, [60], 3, 100, -1),             # short base
+        synth.make_queries(a, b, [160], 3, 100, -1),            # short base
         synth.make_queries(a, b, [0], 4096 - 8, 8, +1),         # largest union
     ])
     got = store.evaluate(q, k=4, tau=0.05)
@@ -355,3 +355,23 @@ def test_budget(wmi):
         b3 = st.submit(small, k=4, nonblocking=True)  # fits once b1 finished
         b3.read()
         b3.destroy()
+
+
+def test_pipelined_replays_and_timing(store, cfg1):
+    """Runs enqueued back to back (direct and graph) leave results unchanged;
+    per-kernel event timings are reported for direct runs."""
+    w, q = cfg1
+    b = store.submit(q, k=4)
+    first = b.read().copy()
+    for _ in range(3):
+        b.replay(direct=True)
+    t = b.timing()
+    assert t["runs"] >= 1 and t["mode"] == 0 and t["main_ms"] > 0 and t["prep_ms"] > 0
+    assert t["total_ms"] >= t["main_ms"]
+    for _ in range(3):
+        b.replay()
+    b.replay(direct=True)
+    again = b.read()
+    assert np.array_equal(first.view(np.uint8), again.view(np.uint8))
+    assert b.timing()["mode"] == -1  # mixed graph and direct runs
+    b.destroy()
