@@ -231,7 +231,7 @@ def test_noise_triples_config3_sample(store, orc):
 
 
 def test_left_and_right_triples_and_short_windows(store, orc):
-    x, y = synth.relation("quadratic", 3000, 21)
+    x, y = synth.relation("quadratic", 5000, 21)
     a, b = store.add_series(x), store.add_series(y)
     q = np.concatenate([
         synth.make_queries(a, b, [100, 700, 1500], 300, 60, +1),
