@@ -293,18 +293,20 @@ def test_offgrid_flag_and_device_series(store, orc):
 def test_errors(wmi, store):
     x, y = synth.relation("linear", 300, 1)
     a, b = store.add_series(x), store.add_series(y)
-    bad = [
-        synth.make_queries(a, 999, 0, 64),                 # unknown series
-        synth.make_queries(a, b, 250, 64),                 # past the end
-        synth.make_queries(a, b, 0, 0),                    # empty window
-        synth.make_queries(a, b, 10, 64, 8, -1),           # left extension before start
-        synth.make_queries(a, b, 0, 100, 0, +1),           # empty extension
-        synth.make_queries(a, b, 0, 64, 8, 2),             # bad side
-    ]
-    for q in bad:
+    bad = {
+        "unknown series": synth.make_queries(a, 999, 0, 64),
+        "past the end": synth.make_queries(a, b, 250, 64),
+        "empty window": synth.make_queries(a, b, 0, 0),
+        "left extension before start": synth.make_queries(a, b, 5, 64, 8, -1),
+        "right extension past the end": synth.make_queries(a, b, 200, 64, 40, +1),
+        "empty extension": synth.make_queries(a, b, 0, 100, 0, +1),
+        "bad side": synth.make_queries(a, b, 0, 64, 8, 2),
+        "window above the maximum": synth.make_queries(a, b, 0, 4097),
+    }
+    for name, q in bad.items():
         with pytest.raises(wmi.WmiError) as e:
             store.submit(q, k=4)
-        assert e.value.code == wmi.WMI_EINVAL
+        assert e.value.code == wmi.WMI_EINVAL, name
     q = synth.make_queries(a, b, 0, 64)
     for kw in ({"k": 0}, {"k": 17}, {"estimator": 2}):
         with pytest.raises(wmi.WmiError) as e:
