@@ -2,8 +2,13 @@
 //
 // HBM layout of one launch (all arrays carved from one batch allocation):
 //   WinDesc  win[W]      one per window (a noise triple contributes three)
-//   Item     item[I]     kNN work items: (window, first query point); sorted by
-//                        cost m * points, largest first, for the persistent form
+//   Item     item[I]     work items, largest first: a split item is one block
+//                        of query points of a window above kLocalSlots points;
+//                        a local item is up to kLocalWindows consecutive
+//                        windows (whole queries where they fit) done entirely
+//                        inside one workgroup
+//   u32      prep[Np]    the split windows (their marginals are sorted by the
+//                        prep kernel; local items sort in LDS)
 //   QDesc    qd[Qn]      one per query: its first window, window count, tau
 //   int32    sorted[2*P] per window, its x and y grid integers in ascending
 //                        order (P = sum of m); written by the prep kernel
@@ -25,6 +30,12 @@ constexpr int kFixShift = 44;         // fixed-point scale of the digamma sums
 
 constexpr uint32_t kFlagNoise = 1u, kFlagTooShort = 2u, kFlagNonPos = 4u, kFlagOffGrid = 8u;
 
+constexpr int kSplitPoints = 2 * kBlock;  // query points per split item
+constexpr int kLocalSlots = 2 * kBlock;   // points (each window padded to even) per local item
+constexpr int kLocalWindows = 16;         // windows per local item
+constexpr int kLocalSort = 1024;          // windows x pow2(max m) per local item
+constexpr uint32_t kItemLocal = 0x80000000u;
+
 struct WinDesc {            // 32 bytes
     const float *x;         // series a + window start
     const float *y;         // series b + window start
@@ -35,8 +46,8 @@ struct WinDesc {            // 32 bytes
 };
 
 struct Item {               // 8 bytes
-    uint32_t win;
-    uint32_t q0;            // first query point of the item
+    uint32_t win;           // split: the window; local: its first window
+    uint32_t info;          // split: first query point; local: kItemLocal | windows
 };
 
 struct QDesc {              // 16 bytes
@@ -78,7 +89,9 @@ struct LaunchArgs {
     uint32_t k;
     uint32_t estimator;
     uint32_t persistent;          // 1: take items from *counter; 0: blockIdx.x
-    uint32_t win_begin;           // prep kernel: first window of this launch
+    uint32_t win_begin;           // prep kernel: first entry of prep_list for this launch
+    const uint32_t *prep_list;    // windows the prep kernel sorts (split windows)
+    uint32_t n_prep;
     // debug export (one window): per point counts and radii, or null
     uint32_t *dbg_nx, *dbg_ny;
     float *dbg_ex, *dbg_ey;

@@ -8,30 +8,33 @@
 // neighbours and marginal counts inside the radii (the worked example of
 // Section 7.1.1: counts use <= and include the neighbours, not the point).
 //
-// Work split (no MFMA anywhere: a max-norm neighbour search is not a
-// contraction; the bound is the 32-bit VALU):
-//   prep_kernel  one workgroup per window: converts the window to grid
-//                integers (v * 2^12), finds its minima, checks the grid, and
-//                sorts each marginal in LDS (bitonic) into HBM.
-//   main_kernel  persistent: workgroups take (window, query block) items from
-//                an atomic counter, largest first.  Per item the window is
-//                staged in LDS as 32-bit keys; each lane scans all m
-//                candidates for up to Q query points, keeping the k+1
-//                smallest keys in registers with a med3 insertion network
-//                (no sort, no branch); the point itself is dropped at the end.
-//                Marginal counts come from two binary searches per dimension
-//                in the sorted marginals.  Digamma terms are summed exactly in
-//                64-bit fixed point with integer atomics, so the result does
-//                not depend on how the window was split or scheduled.  The
-//                last item of a window forms the estimate in double precision;
-//                the last window of a query applies Definition 6.2.
+// No MFMA anywhere: a max-norm neighbour search is not a contraction; the
+// bound is the 32-bit VALU.  Work comes in two kinds of items, taken
+// largest first from an atomic counter by a persistent kernel:
 //
-// Keys.  With grid integers X = v * 2^12 and U = (X - min) << nb, where
-// 2^nb >= m, the key of candidate j for query i is
+//   local item  up to 16 consecutive windows of at most 512 points in total
+//               (whole queries, noise triples included, where they fit).
+//               One workgroup stages them in LDS, finds every point's
+//               neighbours, sorts each window's marginals in LDS (bitonic),
+//               counts by binary search, sums digamma terms with LDS integer
+//               atomics and writes the results: no global atomics, no fences.
+//   split item  512 query points of a window above 512 points.  The prep
+//               kernel sorts such windows' marginals into HBM beforehand;
+//               items add exact fixed-point digamma sums with integer
+//               atomics and the last item of a window forms its estimate.
+//
+// Neighbour search.  Each lane owns query points and scans all m candidates
+// of its window from LDS, keeping the k+1 smallest 32-bit keys in registers
+// with a branch-free med3 insertion network; the point itself is dropped at
+// the end.  With grid integers X = v * 2^12 and U = (X - min) << nb,
+// 2^nb >= m, the key of candidate j is
 //   max(|Ux_i - Ux_j| + j, |Uy_i - Uy_j| + j) = (d_ij << nb) | j,
-// so unsigned order is the lexicographic order of (distance, index): ties
-// go to the earlier time index.  Two v_sad_u32 and one v_max_u32 build it.
-// A window whose value range does not fit 32 - nb bits uses 64-bit keys.
+// so unsigned order is the order of (distance, index): ties go to the earlier
+// time index.  Two v_sad_u32 and one v_max_u32 build a key.  A window whose
+// value range does not fit 32 - nb bits uses 64-bit keys (d << 12 | j).
+//
+// Cross-workgroup results travel only through returning atomics issued in
+// order (an s_waitcnt between them); no cache write-back fences are used.
 #include <hip/hip_runtime.h>
 
 #include "wmi_internal.h"
@@ -141,9 +144,10 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
     __shared__ int32_t sy[kMaxWindow];
     __shared__ int32_t s_red[5];
 
-    const uint32_t w = a.win_begin + blockIdx.x;
-    if (w >= a.n_win)
+    const uint32_t pi = a.win_begin + blockIdx.x;
+    if (pi >= a.n_prep)
         return;
+    const uint32_t w = a.prep_list[pi];
     const WinDesc d = a.win[w];
     const int m = (int)d.m;
     const int tid = threadIdx.x;
@@ -228,15 +232,143 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
 }
 
 // --------------------------------------------------------------------------
-// main: k nearest neighbours, marginal counts, digamma sums, completion
+// cross-workgroup values: returning atomics only
 // --------------------------------------------------------------------------
 
-// 32-bit keys.  Lane query i = q0 + tid + q * kBlock.  Outputs the radii in
-// grid units (estimator 0: per dimension; 1: the joint k-th distance).
+// Wait until this thread's outstanding memory operations have returned, so a
+// following atomic is performed after them.  A wait instruction only.
+__device__ __forceinline__ void wait_returned() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ void publish_f64(double *p, double v)
+{
+    atomicExch(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ double fetch_f64(double *p)
+{
+    return __longlong_as_double((long long)atomicAdd(reinterpret_cast<unsigned long long *>(p), 0ull));
+}
+
+// Result of a query from its windows' estimates (Definition 6.2 for triples).
+__device__ __forceinline__ Result compose_result(const QDesc &qd, const double *mi, const uint32_t *fl)
+{
+    Result r;
+    r.reserved = 0u;
+    const double nan = __builtin_nan("");
+    if (qd.nwin == 1) {
+        r.mi_base = mi[0];
+        r.mi_ext = nan;
+        r.mi_union = nan;
+        r.flags = fl[0];
+        return r;
+    }
+    uint32_t f = fl[0] | fl[1] | fl[2];
+    if (!(f & kFlagTooShort)) {
+        if (!(mi[0] > 0.0))
+            f |= kFlagNonPos;
+        else if (mi[1] < qd.tau_eff && mi[2] < mi[0])
+            f |= kFlagNoise;
+    }
+    r.mi_base = mi[0];
+    r.mi_ext = mi[1];
+    r.mi_union = mi[2];
+    r.flags = f;
+    return r;
+}
+
+// A window's final estimate, reported to its query by one thread.  A plain
+// query is written directly; a triple whose windows finished in different
+// workgroups is completed by whichever finishes last.
+__device__ void report_window(const LaunchArgs &a, uint32_t w, uint32_t q, double mi, uint32_t fl)
+{
+    const QDesc qd = a.qd[q];
+    if (qd.nwin == 1) {
+        a.res[q] = compose_result(qd, &mi, &fl);
+        return;
+    }
+    publish_f64(&a.wmi[w], mi);
+    atomicExch(&a.wflags[w], fl);
+    wait_returned();
+    uint32_t prev = atomicAdd(&a.qdone[q], 1u);
+    if (prev + 1u == qd.nwin) {
+        double m3[3];
+        uint32_t f3[3];
+        for (int r = 0; r < 3; ++r) {
+            m3[r] = fetch_f64(&a.wmi[qd.win0 + r]);
+            f3[r] = atomicAdd(&a.wflags[qd.win0 + r], 0u);
+        }
+        a.res[q] = compose_result(qd, m3, f3);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ double window_estimate(const LaunchArgs &a, int m, long long S)
+{
+    double Sd = (double)S * 0x1p-44;
+    if (a.estimator == 0)
+        return (a.psi_d[K] - 1.0 / (double)K + a.psi_d[m]) - Sd / (double)m;
+    return (a.psi_d[K] + a.psi_d[m]) - Sd / (double)m;
+}
+
+// Marginal counts of a point from the sorted marginals of its window, and the
+// fixed-point digamma terms (Eq. 2; estimator 1 uses psi(n + 1)).
+__device__ __forceinline__ long long count_terms(const LaunchArgs &a, const int32_t *sx, const int32_t *sy,
+                                                 int m, int32_t xi, int32_t yi, int32_t ex, int32_t ey,
+                                                 int &cx, int &cy)
+{
+    if (a.estimator == 0) {
+        cx = count_le(sx, m, xi + ex) - count_lt(sx, m, xi - ex) - 1;
+        cy = count_le(sy, m, yi + ey) - count_lt(sy, m, yi - ey) - 1;
+        return a.psi_fix[cx] + a.psi_fix[cy];
+    }
+    // strict counts inside the joint radius; a zero radius counts nothing
+    // (the open interval is empty), otherwise the point itself is inside
+    if (ex > 0) {
+        cx = count_lt(sx, m, xi + ex) - count_le(sx, m, xi - ex) - 1;
+        cy = count_lt(sy, m, yi + ey) - count_le(sy, m, yi - ey) - 1;
+    } else {
+        cx = 0;
+        cy = 0;
+    }
+    return a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
+}
+
+// Neighbours of one query from its k+1 smallest keys: drop the point itself
+// (key i: distance 0, index i), then the radii in grid units.
+template <int K, typename T>
+__device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, int shift, uint32_t mask, int m,
+                                                const uint32_t *cand, uint32_t base, uint32_t qx, uint32_t qy,
+                                                int dshift, uint32_t est, uint32_t &rx, uint32_t &ry)
+{
+    T nbk[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        nbk[r] = top[r] < self ? top[r] : top[r + 1];
+    if (est == 0) {
+        uint32_t ex = 0, ey = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            uint32_t jj = min((uint32_t)(nbk[r] & (T)mask), (uint32_t)(m - 1));
+            uint32_t cx = cand[2 * (base + jj)] >> dshift, cy = cand[2 * (base + jj) + 1] >> dshift;
+            uint32_t px = qx >> dshift, py = qy >> dshift;
+            ex = tmax(ex, px > cx ? px - cx : cx - px);
+            ey = tmax(ey, py > cy ? py - cy : cy - py);
+        }
+        rx = ex;
+        ry = ey;
+    } else {
+        rx = (uint32_t)(nbk[K - 1] >> shift);
+        ry = rx;
+    }
+}
+
+// --------------------------------------------------------------------------
+// split items: one block of up to 512 query points of a large window
+// --------------------------------------------------------------------------
+
+// 32-bit keys.  Lane query i = q0 + tid + q * kBlock.
 template <int K, int Q>
-__device__ __forceinline__ void knn_narrow(const uint32_t *__restrict__ cand, int m, uint32_t nb,
-                                           int q0, int tid, uint32_t est, uint32_t (&rx)[Q],
-                                           uint32_t (&ry)[Q])
+__device__ __forceinline__ void split_knn_narrow(const uint32_t *__restrict__ cand, int m, uint32_t nb, int q0,
+                                                 int tid, uint32_t est, uint32_t (&rx)[Q], uint32_t (&ry)[Q])
 {
     constexpr int S = K + 1;
     uint32_t qx[Q], qy[Q];
@@ -252,7 +384,6 @@ __device__ __forceinline__ void knn_narrow(const uint32_t *__restrict__ cand, in
     }
     const uint4 *c4 = reinterpret_cast<const uint4 *>(cand);
     int j = 0;
-#pragma unroll 2
     for (; j + 1 < m; j += 2) {
         uint4 c = c4[j >> 1];
 #pragma unroll
@@ -267,57 +398,38 @@ __device__ __forceinline__ void knn_narrow(const uint32_t *__restrict__ cand, in
         uint32_t cx = cand[2 * j], cy = cand[2 * j + 1];
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            insert_sorted<S>(top[q], tmax(sad_u32(qx[q], cx, (uint32_t)j), sad_u32(qy[q], cy, (uint32_t)j)));
+            insert_sorted<S>(top[q], tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j)));
     }
-    const uint32_t mask = (1u << nb) - 1u;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        // the point itself has key (0 << nb) | i; drop it if it is in the list
         uint32_t self = (uint32_t)min(q0 + tid + q * kBlock, m - 1);
-        uint32_t nbk[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            nbk[r] = top[q][r] < self ? top[q][r] : top[q][r + 1];
-        if (est == 0) {
-            uint32_t ex = 0, ey = 0;
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                uint32_t jj = nbk[r] & mask;
-                ex = tmax(ex, sad_u32(qx[q], cand[2 * jj], 0u));
-                ey = tmax(ey, sad_u32(qy[q], cand[2 * jj + 1], 0u));
-            }
-            rx[q] = ex >> nb;
-            ry[q] = ey >> nb;
-        } else {
-            rx[q] = nbk[K - 1] >> nb;
-            ry[q] = rx[q];
-        }
+        radii_from_keys<K, uint32_t>(top[q], self, (int)nb, (1u << nb) - 1u, m, cand, 0u, qx[q], qy[q], (int)nb, est,
+                                     rx[q], ry[q]);
     }
 }
 
-// 64-bit keys (d << 12 | j) for windows whose range does not fit 32-bit keys;
-// the staged values are the raw grid integers.
+// 64-bit keys (d << 12 | j); the staged values are X - min.
 template <int K, int Q>
-__device__ __forceinline__ void knn_wide(const uint32_t *__restrict__ cand, int m, int q0, int tid,
-                                         uint32_t est, uint32_t (&rx)[Q], uint32_t (&ry)[Q])
+__device__ __forceinline__ void split_knn_wide(const uint32_t *__restrict__ cand, int m, int q0, int tid,
+                                               uint32_t est, uint32_t (&rx)[Q], uint32_t (&ry)[Q])
 {
     constexpr int S = K + 1;
-    int32_t qx[Q], qy[Q];
+    uint32_t qx[Q], qy[Q];
     unsigned long long top[Q][S];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int i = min(q0 + tid + q * kBlock, m - 1);
-        qx[q] = (int32_t)cand[2 * i];
-        qy[q] = (int32_t)cand[2 * i + 1];
+        qx[q] = cand[2 * i];
+        qy[q] = cand[2 * i + 1];
 #pragma unroll
         for (int r = 0; r < S; ++r)
             top[q][r] = ~0ull;
     }
     for (int j = 0; j < m; ++j) {
-        int32_t cx = (int32_t)cand[2 * j], cy = (int32_t)cand[2 * j + 1];
+        uint32_t cx = cand[2 * j], cy = cand[2 * j + 1];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            uint32_t d = (uint32_t)max(abs(qx[q] - cx), abs(qy[q] - cy));
+            uint32_t d = tmax(sad_u32(qx[q], cx, 0u), sad_u32(qy[q], cy, 0u));
             unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
             if (key < top[q][S - 1])
                 insert_sorted<S>(top[q], key);
@@ -326,54 +438,31 @@ __device__ __forceinline__ void knn_wide(const uint32_t *__restrict__ cand, int 
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         unsigned long long self = (unsigned long long)min(q0 + tid + q * kBlock, m - 1);
-        unsigned long long nbk[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            nbk[r] = top[q][r] < self ? top[q][r] : top[q][r + 1];
-        if (est == 0) {
-            uint32_t ex = 0, ey = 0;
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                uint32_t jj = (uint32_t)(nbk[r] & 0xFFFull);
-                ex = tmax(ex, (uint32_t)abs(qx[q] - (int32_t)cand[2 * jj]));
-                ey = tmax(ey, (uint32_t)abs(qy[q] - (int32_t)cand[2 * jj + 1]));
-            }
-            rx[q] = ex;
-            ry[q] = ey;
-        } else {
-            rx[q] = (uint32_t)(nbk[K - 1] >> 12);
-            ry[q] = rx[q];
-        }
+        radii_from_keys<K, unsigned long long>(top[q], self, 12, 0xFFFu, m, cand, 0u, qx[q], qy[q], 0, est, rx[q],
+                                               ry[q]);
     }
 }
 
 template <int K, int Q>
-__device__ __forceinline__ long long item_body(const LaunchArgs &a, const WinDesc &d, const WinAux &ax,
-                                               int q0, uint32_t *cand)
+__device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDesc &d, const WinAux &ax, int q0,
+                                                uint32_t *cand)
 {
     const int m = (int)d.m;
     const int tid = threadIdx.x;
     uint32_t rx[Q], ry[Q];
     if (ax.nb)
-        knn_narrow<K, Q>(cand, m, ax.nb, q0, tid, a.estimator, rx, ry);
+        split_knn_narrow<K, Q>(cand, m, ax.nb, q0, tid, a.estimator, rx, ry);
     else
-        knn_wide<K, Q>(cand, m, q0, tid, a.estimator, rx, ry);
-
-    // query grid integers, from the staged values, before they are replaced
+        split_knn_wide<K, Q>(cand, m, q0, tid, a.estimator, rx, ry);
     int32_t xi[Q], yi[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int i = min(q0 + tid + q * kBlock, m - 1);
-        if (ax.nb) {
-            xi[q] = (int32_t)(cand[2 * i] >> ax.nb) + ax.min_x;
-            yi[q] = (int32_t)(cand[2 * i + 1] >> ax.nb) + ax.min_y;
-        } else {
-            xi[q] = (int32_t)cand[2 * i];
-            yi[q] = (int32_t)cand[2 * i + 1];
-        }
+        xi[q] = (int32_t)(cand[2 * i] >> ax.nb) + ax.min_x;
+        yi[q] = (int32_t)(cand[2 * i + 1] >> ax.nb) + ax.min_y;
     }
     __syncthreads();
-    // stage the sorted marginals over the candidates
+    // the sorted marginals replace the candidates in LDS
     int32_t *sx = reinterpret_cast<int32_t *>(cand);
     int32_t *sy = sx + kMaxWindow;
     const int32_t *src = a.sorted + 2ull * d.sorted_off;
@@ -382,7 +471,6 @@ __device__ __forceinline__ long long item_body(const LaunchArgs &a, const WinDes
         sy[i] = src[m + i];
     }
     __syncthreads();
-
     long long part = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -390,102 +478,378 @@ __device__ __forceinline__ long long item_body(const LaunchArgs &a, const WinDes
         if (i >= m)
             continue;
         int cx, cy;
-        int32_t ex = (int32_t)rx[q], ey = (int32_t)ry[q];
-        if (a.estimator == 0) {
-            cx = count_le(sx, m, xi[q] + ex) - count_lt(sx, m, xi[q] - ex) - 1;
-            cy = count_le(sy, m, yi[q] + ey) - count_lt(sy, m, yi[q] - ey) - 1;
-            part += a.psi_fix[cx] + a.psi_fix[cy];
-        } else {
-            // strict counts inside the joint radius; a zero radius counts nothing
-            // (the open interval is empty), otherwise the point itself is inside
-            if (ex > 0) {
-                cx = count_lt(sx, m, xi[q] + ex) - count_le(sx, m, xi[q] - ex) - 1;
-                cy = count_lt(sy, m, yi[q] + ey) - count_le(sy, m, yi[q] - ey) - 1;
-            } else {
-                cx = 0;
-                cy = 0;
-            }
-            part += a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
-        }
+        part += count_terms(a, sx, sy, m, xi[q], yi[q], (int32_t)rx[q], (int32_t)ry[q], cx, cy);
         if (a.dbg_nx) {
             a.dbg_nx[i] = (uint32_t)cx;
             a.dbg_ny[i] = (uint32_t)cy;
-            a.dbg_ex[i] = (float)ex * (1.0f / 4096.0f);
-            a.dbg_ey[i] = (float)ey * (1.0f / 4096.0f);
+            a.dbg_ex[i] = (float)rx[q] * (1.0f / 4096.0f);
+            a.dbg_ey[i] = (float)ry[q] * (1.0f / 4096.0f);
         }
     }
     return part;
 }
 
-__device__ void finalize_query(const LaunchArgs &a, uint32_t query)
+template <int K>
+__device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *cand, long long *s_part)
 {
-    const QDesc qd = a.qd[query];
-    Result r;
-    r.reserved = 0u;
-    const double nan = __builtin_nan("");
-    if (qd.nwin == 1) {
-        r.mi_base = a.wmi[qd.win0];
-        r.mi_ext = nan;
-        r.mi_union = nan;
-        r.flags = a.wflags[qd.win0];
-    } else {
-        double b = a.wmi[qd.win0], e = a.wmi[qd.win0 + 1], u = a.wmi[qd.win0 + 2];
-        uint32_t f = a.wflags[qd.win0] | a.wflags[qd.win0 + 1] | a.wflags[qd.win0 + 2];
-        if (!(f & kFlagTooShort)) {
-            if (!(b > 0.0))
-                f |= kFlagNonPos;
-            else if (e < qd.tau_eff && u < b)
-                f |= kFlagNoise;
+    const WinDesc d = a.win[w];
+    const WinAux ax = a.aux[w];
+    const int m = (int)d.m;
+    const int tid = threadIdx.x;
+    long long part = 0;
+    if (m > K) {
+        // stage the window: 32-bit keys, or X - min for the 64-bit path
+        uint32_t off = 0;
+        for (int i = tid; i < m; i += kBlock) {
+            int32_t xi = grid_int(d.x[i], off);
+            int32_t yi = grid_int(d.y[i], off);
+            cand[2 * i] = (uint32_t)(xi - ax.min_x) << ax.nb;
+            cand[2 * i + 1] = (uint32_t)(yi - ax.min_y) << ax.nb;
         }
-        r.mi_base = b;
-        r.mi_ext = e;
-        r.mi_union = u;
-        r.flags = f;
+        __syncthreads();
+        if (m - q0 <= kBlock)
+            part = split_body<K, 1>(a, d, ax, q0, cand);
+        else
+            part = split_body<K, 2>(a, d, ax, q0, cand);
     }
-    a.res[query] = r;
+    // workgroup sum of the fixed-point terms (exact, order-free)
+    for (int o = 32; o > 0; o >>= 1)
+        part += __shfl_xor(part, o, 64);
+    if ((tid & 63) == 0)
+        s_part[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) {
+        long long tot = 0;
+        for (int wv = 0; wv < kBlock / 64; ++wv)
+            tot += s_part[wv];
+        unsigned long long seen = 0;
+        if (m > K)
+            seen = atomicAdd(&a.acc[w], (unsigned long long)tot);
+        (void)seen;
+        wait_returned();
+        uint32_t prev = atomicAdd(&a.wdone[w], 1u);
+        if (prev + 1u == d.n_items) {
+            double mi;
+            uint32_t fl = ax.flags;
+            if (m <= K) {
+                mi = __builtin_nan("");
+                fl |= kFlagTooShort;
+            } else {
+                long long S = (long long)atomicAdd(&a.acc[w], 0ull);
+                mi = window_estimate<K>(a, m, S);
+            }
+            a.wmi[w] = mi;
+            a.wflags[w] = fl;
+            report_window(a, w, d.query, mi, fl);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// local items: up to 16 consecutive windows, all inside one workgroup
+// --------------------------------------------------------------------------
+
+struct LocalShared {
+    const float *x[kLocalWindows];
+    const float *y[kLocalWindows];
+    unsigned long long acc[kLocalWindows];
+    double mi[kLocalWindows];
+    uint32_t off[kLocalWindows + 1];
+    uint32_t m[kLocalWindows];
+    uint32_t nb[kLocalWindows];
+    uint32_t flags[kLocalWindows];
+    uint32_t query[kLocalWindows];
+    int32_t mn[2][kLocalWindows];
+    int32_t mx[2][kLocalWindows];
+    uint32_t P, log2P;
+};
+
+// One slot's neighbour search inside a local item.  mode 0: every active lane
+// of the wave has the same m and 32-bit keys; 1: 32-bit keys, lanes with
+// different m (masked); 2: 64-bit keys.  m_loop is the wave's largest m.
+template <int K>
+__device__ __forceinline__ void local_knn(const uint32_t *__restrict__ cand, uint32_t base, int m, int i,
+                                          uint32_t nb, int mode, int m_loop, uint32_t est, uint32_t &rx,
+                                          uint32_t &ry)
+{
+    constexpr int S = K + 1;
+    const uint32_t qx = cand[2 * (base + i)], qy = cand[2 * (base + i) + 1];
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(cand + 2 * base);
+    if (mode == 0) {
+        uint32_t top[S];
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+            top[r] = 0xFFFFFFFFu;
+        int j = 0;
+        for (; j + 1 < m_loop; j += 2) {
+            uint4 c = c4[j >> 1];
+            insert_sorted<S>(top, tmax(sad_key(qx, c.x, (uint32_t)j), sad_key(qy, c.y, (uint32_t)j)));
+            insert_sorted<S>(top, tmax(sad_key(qx, c.z, (uint32_t)j + 1u), sad_key(qy, c.w, (uint32_t)j + 1u)));
+        }
+        if (j < m_loop) {
+            uint32_t cx = cand[2 * (base + j)], cy = cand[2 * (base + j) + 1];
+            insert_sorted<S>(top, tmax(sad_key(qx, cx, (uint32_t)j), sad_key(qy, cy, (uint32_t)j)));
+        }
+        radii_from_keys<K, uint32_t>(top, (uint32_t)i, (int)nb, (1u << nb) - 1u, m, cand, base, qx, qy, (int)nb, est,
+                                     rx, ry);
+    } else if (mode == 1) {
+        uint32_t top[S];
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+            top[r] = 0xFFFFFFFFu;
+        int j = 0;
+        for (; j + 1 < m_loop; j += 2) {
+            uint4 c = c4[j >> 1];
+            uint32_t k0 = tmax(sad_key(qx, c.x, (uint32_t)j), sad_key(qy, c.y, (uint32_t)j));
+            uint32_t k1 = tmax(sad_key(qx, c.z, (uint32_t)j + 1u), sad_key(qy, c.w, (uint32_t)j + 1u));
+            insert_sorted<S>(top, j < m ? k0 : 0xFFFFFFFFu);
+            insert_sorted<S>(top, j + 1 < m ? k1 : 0xFFFFFFFFu);
+        }
+        if (j < m_loop) {
+            uint32_t cx = cand[2 * (base + j)], cy = cand[2 * (base + j) + 1];
+            uint32_t k0 = tmax(sad_key(qx, cx, (uint32_t)j), sad_key(qy, cy, (uint32_t)j));
+            insert_sorted<S>(top, j < m ? k0 : 0xFFFFFFFFu);
+        }
+        radii_from_keys<K, uint32_t>(top, (uint32_t)i, (int)nb, (1u << nb) - 1u, m, cand, base, qx, qy, (int)nb, est,
+                                     rx, ry);
+    } else {
+        unsigned long long top[S];
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+            top[r] = ~0ull;
+        const uint32_t px = qx >> nb, py = qy >> nb;
+        for (int j = 0; j < m_loop; ++j) {
+            uint32_t cx = cand[2 * (base + j)] >> nb, cy = cand[2 * (base + j) + 1] >> nb;
+            uint32_t d = tmax(sad_u32(px, cx, 0u), sad_u32(py, cy, 0u));
+            unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
+            if (j < m && key < top[S - 1])
+                insert_sorted<S>(top, key);
+        }
+        radii_from_keys<K, unsigned long long>(top, (unsigned long long)i, 12, 0xFFFu, m, cand, base, qx, qy,
+                                               (int)nb, est, rx, ry);
+    }
 }
 
 template <int K>
-__device__ void finalize_window(const LaunchArgs &a, uint32_t w, const WinDesc &d, const WinAux &ax)
+__device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint32_t *buf, LocalShared &L)
 {
-    const int m = (int)d.m;
-    double mi;
-    uint32_t f = ax.flags;
-    if (m <= K) {
-        mi = __builtin_nan("");
-        f |= kFlagTooShort;
-    } else {
-        long long S = (long long)atomicAdd(&a.acc[w], 0ull);
-        double Sd = (double)S * 0x1p-44;
-        if (a.estimator == 0)
-            mi = (a.psi_d[K] - 1.0 / (double)K + a.psi_d[m]) - Sd / (double)m;
-        else
-            mi = (a.psi_d[K] + a.psi_d[m]) - Sd / (double)m;
+    const int tid = threadIdx.x;
+    uint32_t *cand = buf;                                       // 2 x 1024 words: keys, by slot
+    int32_t *srt_x = reinterpret_cast<int32_t *>(buf + 2 * 1024);  // kLocalSort: sorted marginals
+    int32_t *srt_y = srt_x + kLocalSort;
+
+    if (tid < (int)nwin) {
+        const WinDesc d = a.win[w0 + tid];
+        L.x[tid] = d.x;
+        L.y[tid] = d.y;
+        L.m[tid] = d.m;
+        L.query[tid] = d.query;
+        L.acc[tid] = 0ull;
+        L.flags[tid] = 0u;
+        L.mn[0][tid] = INT32_MAX;
+        L.mn[1][tid] = INT32_MAX;
+        L.mx[0][tid] = INT32_MIN;
+        L.mx[1][tid] = INT32_MIN;
     }
-    a.wmi[w] = mi;
-    a.wflags[w] = f;
-    __threadfence();
-    uint32_t prev = atomicAdd(&a.qdone[d.query], 1u);
-    if (prev + 1u == a.qd[d.query].nwin) {
-        __threadfence();
-        finalize_query(a, d.query);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t off = 0, mmax = 2;
+        for (uint32_t w = 0; w < nwin; ++w) {
+            L.off[w] = off;
+            off += (L.m[w] + 1u) & ~1u;  // even offsets keep 16-byte candidate reads aligned
+            mmax = max(mmax, L.m[w]);
+        }
+        L.off[nwin] = off;
+        uint32_t lp = ceil_log2(mmax);
+        L.P = 1u << lp;
+        L.log2P = lp;
+    }
+    __syncthreads();
+    const uint32_t total = L.off[nwin];
+    const uint32_t P = L.P, lp = L.log2P;
+
+    // ---- stage: grid integers into the sort segments, per-window extrema
+    int32_t X[2], Y[2];
+    uint32_t W[2];
+    int I[2];
+    bool act[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t s = (uint32_t)tid + (uint32_t)(q * kBlock);
+        uint32_t w = 0;
+        while (w + 1 < nwin && L.off[w + 1] <= s)
+            ++w;
+        const int i = (int)s - (int)L.off[w];
+        act[q] = s < total && i < (int)L.m[w];
+        W[q] = w;
+        I[q] = act[q] ? i : 0;
+        X[q] = 0;
+        Y[q] = 0;
+        if (act[q]) {
+            uint32_t off = 0;
+            X[q] = grid_int(L.x[w][i], off);
+            Y[q] = grid_int(L.y[w][i], off);
+            srt_x[(w << lp) + i] = X[q];
+            srt_y[(w << lp) + i] = Y[q];
+            atomicMin(&L.mn[0][w], X[q]);
+            atomicMax(&L.mx[0][w], X[q]);
+            atomicMin(&L.mn[1][w], Y[q]);
+            atomicMax(&L.mx[1][w], Y[q]);
+            if (off)
+                atomicOr(&L.flags[w], kFlagOffGrid);
+        }
+    }
+    for (uint32_t t = tid; t < (nwin << lp); t += kBlock) {
+        const uint32_t w = t >> lp, i = t & (P - 1u);
+        if (i >= L.m[w]) {
+            srt_x[t] = INT32_MAX;
+            srt_y[t] = INT32_MAX;
+        }
+    }
+    __syncthreads();
+    if (tid < (int)nwin) {
+        const uint32_t m = L.m[tid];
+        const uint32_t nb = ceil_log2(m > 1 ? m : 2u);
+        const uint32_t rxr = (uint32_t)(L.mx[0][tid] - L.mn[0][tid]);
+        const uint32_t ryr = (uint32_t)(L.mx[1][tid] - L.mn[1][tid]);
+        L.nb[tid] = (((rxr | ryr) >> (32 - nb)) == 0u) ? nb : 0u;
+    }
+    __syncthreads();
+    // ---- keys (or X - min for the 64-bit path), by slot
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (act[q]) {
+            const uint32_t s = (uint32_t)tid + (uint32_t)(q * kBlock);
+            const uint32_t w = W[q], nb = L.nb[w];
+            cand[2 * s] = (uint32_t)(X[q] - L.mn[0][w]) << nb;
+            cand[2 * s + 1] = (uint32_t)(Y[q] - L.mn[1][w]) << nb;
+        }
+    }
+    __syncthreads();
+
+    // ---- neighbours: one pass per slot of the thread
+    uint32_t RX[2] = {0u, 0u}, RY[2] = {0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const bool live = act[q] && (int)L.m[W[q]] > K;
+        const unsigned long long bal = __ballot(live);
+        if (bal == 0ull)
+            continue;  // wave-uniform
+        // lanes without a live slot follow the first live lane's window
+        const int first = __ffsll((long long)bal) - 1;
+        const uint32_t lead_w = (uint32_t)__shfl((int)W[q], first, 64);
+        const uint32_t wl = live ? W[q] : lead_w;
+        const int il = live ? I[q] : 0;
+        const int m = (int)L.m[wl];
+        const uint32_t nb = L.nb[wl];
+        // wave-wide: same m everywhere?  any 64-bit window?  largest m?
+        int m_max = m, m_min = m;
+        uint32_t nb_min = nb;
+        for (int o = 32; o > 0; o >>= 1) {
+            m_max = max(m_max, __shfl_xor(m_max, o, 64));
+            m_min = min(m_min, __shfl_xor(m_min, o, 64));
+            nb_min = min(nb_min, (uint32_t)__shfl_xor((int)nb_min, o, 64));
+        }
+        const int mode = nb_min == 0u ? 2 : (m_max == m_min ? 0 : 1);
+        local_knn<K>(cand, L.off[wl], m, il, nb, mode, m_max, a.estimator, RX[q], RY[q]);
+    }
+    __syncthreads();
+
+    // ---- sort every window's marginals (segments of P, padded with INT32_MAX)
+    const uint32_t npairs = (nwin << lp) >> 1;
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = tid; t < npairs; t += kBlock) {
+                const uint32_t lo = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u));
+                const uint32_t hi = lo + stride;
+                const bool asc = (lo & size) == 0u;
+                int32_t a0 = srt_x[lo], a1 = srt_x[hi];
+                if ((a0 > a1) == asc) {
+                    srt_x[lo] = a1;
+                    srt_x[hi] = a0;
+                }
+                int32_t b0 = srt_y[lo], b1 = srt_y[hi];
+                if ((b0 > b1) == asc) {
+                    srt_y[lo] = b1;
+                    srt_y[hi] = b0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- counts and digamma terms
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (!act[q])
+            continue;
+        const uint32_t w = W[q];
+        const int m = (int)L.m[w];
+        if (m <= K)
+            continue;
+        int cx, cy;
+        long long t = count_terms(a, srt_x + (w << lp), srt_y + (w << lp), m, X[q], Y[q], (int32_t)RX[q],
+                                  (int32_t)RY[q], cx, cy);
+        atomicAdd(&L.acc[w], (unsigned long long)t);
+        if (a.dbg_nx) {
+            a.dbg_nx[I[q]] = (uint32_t)cx;
+            a.dbg_ny[I[q]] = (uint32_t)cy;
+            a.dbg_ex[I[q]] = (float)RX[q] * (1.0f / 4096.0f);
+            a.dbg_ey[I[q]] = (float)RY[q] * (1.0f / 4096.0f);
+        }
+    }
+    __syncthreads();
+
+    // ---- estimates, then results
+    if (tid < (int)nwin) {
+        const int m = (int)L.m[tid];
+        uint32_t fl = L.flags[tid];
+        double mi;
+        if (m <= K) {
+            mi = __builtin_nan("");
+            fl |= kFlagTooShort;
+        } else {
+            mi = window_estimate<K>(a, m, (long long)L.acc[tid]);
+        }
+        L.mi[tid] = mi;
+        L.flags[tid] = fl;
+        a.wmi[w0 + tid] = mi;
+        a.wflags[w0 + tid] = fl;
+    }
+    __syncthreads();
+    if (tid < (int)nwin) {
+        const uint32_t w = w0 + tid, q = L.query[tid];
+        const QDesc qd = a.qd[q];
+        const bool inside = qd.win0 >= w0 && qd.win0 + qd.nwin <= w0 + nwin;
+        if (inside) {
+            if (qd.win0 == w)
+                a.res[q] = compose_result(qd, &L.mi[tid], &L.flags[tid]);
+        } else {
+            report_window(a, w, q, L.mi[tid], L.flags[tid]);
+        }
     }
 }
 
+// --------------------------------------------------------------------------
+// main: persistent loop over items
+// --------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
 {
-    __shared__ __align__(16) uint32_t cand[2 * kMaxWindow];
+    __shared__ __align__(16) uint32_t buf[2 * kMaxWindow];
+    __shared__ LocalShared L;
     __shared__ long long s_part[kBlock / 64];
-    __shared__ uint32_t s_item, s_last;
+    __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
 
+    if (a.persistent) {
+        if (tid == 0)
+            s_item = atomicAdd(a.counter, 1u);
+        __syncthreads();
+    }
     for (uint32_t iter = 0;; ++iter) {
         uint32_t it;
         if (a.persistent) {
-            if (tid == 0)
-                s_item = atomicAdd(a.counter, 1u);
-            __syncthreads();
             it = s_item;
         } else {
             if (iter > 0)
@@ -494,52 +858,18 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
         }
         if (it >= a.n_items)
             break;
+        // fetch the next item now; its latency overlaps this item's work
+        uint32_t next = 0;
+        if (a.persistent && tid == 0)
+            next = atomicAdd(a.counter, 1u);
         const Item itm = a.item[a.item_begin + it];
-        const WinDesc d = a.win[itm.win];
-        const WinAux ax = a.aux[itm.win];
-        const int m = (int)d.m;
-        long long part = 0;
-        if (m > K) {
-            // stage the window as keys (32-bit) or raw grid integers (64-bit path)
-            uint32_t off = 0;
-            for (int i = tid; i < m; i += kBlock) {
-                int32_t xi = grid_int(d.x[i], off);
-                int32_t yi = grid_int(d.y[i], off);
-                if (ax.nb) {
-                    cand[2 * i] = (uint32_t)(xi - ax.min_x) << ax.nb;
-                    cand[2 * i + 1] = (uint32_t)(yi - ax.min_y) << ax.nb;
-                } else {
-                    cand[2 * i] = (uint32_t)xi;
-                    cand[2 * i + 1] = (uint32_t)yi;
-                }
-            }
-            __syncthreads();
-            const int q0 = (int)itm.q0;
-            if (m - q0 <= kBlock)
-                part = item_body<K, 1>(a, d, ax, q0, cand);
-            else
-                part = item_body<K, 2>(a, d, ax, q0, cand);
-        }
-        // workgroup sum of the fixed-point terms (exact, order-free)
-        for (int o = 32; o > 0; o >>= 1)
-            part += __shfl_xor(part, o, 64);
-        if ((tid & 63) == 0)
-            s_part[tid >> 6] = part;
+        if (itm.info & kItemLocal)
+            local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
+        else
+            split_item<K>(a, itm.win, (int)itm.info, buf, s_part);
         __syncthreads();
-        if (tid == 0) {
-            long long tot = 0;
-            for (int wv = 0; wv < kBlock / 64; ++wv)
-                tot += s_part[wv];
-            if (m > K)
-                atomicAdd(&a.acc[itm.win], (unsigned long long)tot);
-            __threadfence();
-            uint32_t prev = atomicAdd(&a.wdone[itm.win], 1u);
-            s_last = (prev + 1u == d.n_items) ? 1u : 0u;
-            if (s_last) {
-                __threadfence();
-                finalize_window<K>(a, itm.win, d, ax);
-            }
-        }
+        if (a.persistent && tid == 0)
+            s_item = next;
         __syncthreads();
     }
 }

@@ -1,0 +1,138 @@
+// wmi_plan.h -- host-side work list of a batch (no HIP dependency).
+//
+// Windows above kLocalSlots points are split into blocks of kSplitPoints
+// query points; their marginals are sorted by the prep kernel (prep_list).
+// The other windows are packed, in window order, into local items of at most
+// kLocalWindows consecutive windows, kLocalSlots points (each window padded
+// to an even count) and kLocalSort sort entries (windows x the power of two
+// at or above the largest m).  A query whose windows are all local and fit one
+// item is never cut across items; otherwise its windows may land in several
+// items and the kernel completes it with atomics.  In the plain form every
+// window is alone.  Items carry a cost (work estimate) for largest-first
+// ordering.
+#pragma once
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "wmi_internal.h"
+
+namespace wmi {
+
+struct Plan {
+    std::vector<Item> items;
+    std::vector<uint64_t> cost;
+    std::vector<uint32_t> prep_list;   // split windows
+    std::vector<uint32_t> wsorted;     // per window: offset of its sorted marginals (split windows)
+    std::vector<uint32_t> wnitems;     // per window: split items (1 for local windows)
+    std::vector<uint32_t> first_item;  // plain form: first item of each window, plus the end
+    std::vector<int32_t> wprep;        // plain form: prep-list entry of each window, or -1
+    uint64_t split_pts = 0;
+};
+
+inline uint32_t plan_pow2(uint32_t v)
+{
+    uint32_t P = 1;
+    while (P < v)
+        P <<= 1;
+    return P;
+}
+
+// wm[w]: points of window w; wquery[w]: its query (non-decreasing, every query
+// in [0, count) present).
+inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wquery, uint64_t count,
+                       bool plain, Plan &out)
+{
+    const uint64_t n_win = wm.size();
+    out = Plan();
+    out.wsorted.assign(n_win, 0);
+    out.wnitems.assign(n_win, 1);
+    if (plain) {
+        out.first_item.reserve(n_win + 1);
+        out.wprep.assign(n_win, -1);
+    }
+    struct Cur {
+        uint32_t start = 0, n = 0, slots = 0, maxm = 0;
+        uint64_t cost = 0;
+    } cur;
+    auto fits = [](const Cur &c, uint32_t m) {
+        uint32_t maxm = std::max(std::max(c.maxm, m), 2u);
+        return c.n + 1 <= (uint32_t)kLocalWindows && c.slots + ((m + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
+               (c.n + 1) * plan_pow2(maxm) <= (uint32_t)kLocalSort;
+    };
+    auto add = [](Cur &c, uint32_t w, uint32_t m) {
+        if (c.n == 0)
+            c.start = w;
+        c.n++;
+        c.slots += (m + 1u) & ~1u;
+        c.maxm = std::max(c.maxm, m);
+        c.cost += (uint64_t)m * m + 4096u;  // fixed per-window share of the item's overhead
+    };
+    auto close = [&]() {
+        if (cur.n) {
+            out.items.push_back(Item{cur.start, kItemLocal | cur.n});
+            out.cost.push_back(cur.cost);
+        }
+        cur = Cur();
+    };
+    uint32_t w = 0;
+    for (uint64_t t = 0; t < count; ++t) {
+        const uint32_t w0 = w;
+        uint32_t nw = 0;
+        while (w0 + nw < n_win && wquery[w0 + nw] == (uint32_t)t)
+            ++nw;
+        if (!plain) {
+            // start a fresh item rather than cut a query that fits in one
+            bool all_local = true, whole = true;
+            Cur sim;
+            for (uint32_t r = 0; r < nw; ++r) {
+                all_local = all_local && wm[w0 + r] <= (uint32_t)kLocalSlots;
+                if (fits(sim, wm[w0 + r]))
+                    add(sim, w0 + r, wm[w0 + r]);
+                else
+                    whole = false;
+            }
+            if (all_local && whole) {
+                Cur c2 = cur;
+                bool ok = true;
+                for (uint32_t r = 0; r < nw && ok; ++r) {
+                    ok = fits(c2, wm[w0 + r]);
+                    if (ok)
+                        add(c2, w0 + r, wm[w0 + r]);
+                }
+                if (!ok)
+                    close();
+            }
+        }
+        for (uint32_t r = 0; r < nw; ++r, ++w) {
+            const uint32_t m = wm[w];
+            if (plain)
+                out.first_item.push_back((uint32_t)out.items.size());
+            if (m > (uint32_t)kLocalSlots) {
+                close();
+                const uint32_t ni = (m + kSplitPoints - 1) / kSplitPoints;
+                out.wnitems[w] = ni;
+                out.wsorted[w] = (uint32_t)out.split_pts;
+                out.split_pts += m;
+                if (plain)
+                    out.wprep[w] = (int32_t)out.prep_list.size();
+                out.prep_list.push_back(w);
+                for (uint32_t it = 0; it < ni; ++it) {
+                    out.items.push_back(Item{w, it * (uint32_t)kSplitPoints});
+                    out.cost.push_back((uint64_t)std::min<uint32_t>(kSplitPoints, m - it * kSplitPoints) * m);
+                }
+            } else {
+                if (plain || !fits(cur, m))
+                    close();
+                add(cur, w, m);
+                if (plain)
+                    close();
+            }
+        }
+    }
+    close();
+    if (plain)
+        out.first_item.push_back((uint32_t)out.items.size());
+}
+
+}  // namespace wmi

@@ -27,6 +27,7 @@
 
 #include "wmi.h"
 #include "wmi_internal.h"
+#include "wmi_plan.h"
 
 namespace wmi {
 hipError_t launch_clear(const LaunchArgs &a, hipStream_t s);
@@ -45,7 +46,6 @@ static_assert(sizeof(WinDesc) == 32 && sizeof(Item) == 8 && sizeof(QDesc) == 16,
 
 namespace {
 
-constexpr uint32_t kItemPoints = 2 * kBlock;  // query points per work item
 constexpr uint64_t kDefaultBudget = 1ull << 30;
 
 thread_local std::string g_err;
@@ -130,6 +130,7 @@ struct wmi_batch {
     LaunchArgs args{};
     uint32_t grid = 0;
     std::vector<uint32_t> win_first_item;  // plain form: first item of each window
+    std::vector<int32_t> win_prep;         // plain form: prep-list entry of a split window, or -1
     Result *h_res = nullptr;
     Result *d_res = nullptr;
     RunEvents slot[kSlots];
@@ -216,8 +217,10 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
         // baseline form: every window is its own prep launch and main launch
         for (uint32_t w = 0; w < a.n_win; ++w) {
             LaunchArgs aw = a;
-            aw.win_begin = w;
-            HIPCHK(st, launch_prep(aw, 1, s));
+            if (b->win_prep[w] >= 0) {
+                aw.win_begin = (uint32_t)b->win_prep[w];
+                HIPCHK(st, launch_prep(aw, 1, s));
+            }
             aw.item_begin = b->win_first_item[w];
             aw.n_items = b->win_first_item[w + 1] - b->win_first_item[w];
             aw.persistent = 0;
@@ -228,7 +231,7 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
             HIPCHK(st, hipEventRecord(ev->m1, s));
         }
     } else {
-        HIPCHK(st, launch_prep(a, a.n_win, s));
+        HIPCHK(st, launch_prep(a, a.n_prep, s));
         if (ev)
             HIPCHK(st, hipEventRecord(ev->m0, s));
         HIPCHK(st, launch_main(a, b->grid, s));
@@ -634,36 +637,59 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         std::lock_guard<std::mutex> lk(st->mu);
         ser = st->series;
     }
-    uint64_t n_win = 0, n_pts = 0, n_items = 0, pairs = 0;
+    // windows in query order (a triple: base, extension, union)
+    std::vector<uint64_t> wstart;
+    std::vector<uint32_t> wm, wquery;
     std::vector<uint32_t> used;
+    uint64_t pairs = 0;
+    wstart.reserve(count);
+    wm.reserve(count);
+    wquery.reserve(count);
     for (uint64_t t = 0; t < count; ++t) {
         uint64_t s3[3];
         uint32_t m3[3], nw = 0;
         if (int rc = query_windows(qs[t], ser, t, s3, m3, &nw))
             return rc;
         for (uint32_t r = 0; r < nw; ++r) {
-            n_win++;
-            n_pts += m3[r];
-            n_items += std::max<uint64_t>(1, (m3[r] + kItemPoints - 1) / kItemPoints);
+            wstart.push_back(s3[r]);
+            wm.push_back(m3[r]);
+            wquery.push_back((uint32_t)t);
             pairs += (uint64_t)m3[r] * (m3[r] - 1);
         }
         used.push_back(qs[t].a);
         used.push_back(qs[t].b);
     }
-    if (n_win > 0xFFFFFFF0ull || n_pts > 0xFFFFFFF0ull || n_items > 0xFFFFFFF0ull)
-        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu windows, %llu points)",
-                    (unsigned long long)n_win, (unsigned long long)n_pts);
+    const uint64_t n_win = wm.size();
+    if (n_win > 0x7FFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu windows)", (unsigned long long)n_win);
     std::sort(used.begin(), used.end());
     used.erase(std::unique(used.begin(), used.end()), used.end());
+
+    // ---- work items ---------------------------------------------------------
+    const bool plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
+    Plan plan;
+    plan_items(wm, wquery, count, plain, plan);
+    std::vector<Item> &items = plan.items;
+    std::vector<uint64_t> &cost = plan.cost;
+    std::vector<uint32_t> &prep_list = plan.prep_list, &wsorted = plan.wsorted, &wnitems = plan.wnitems,
+                          &first_item = plan.first_item;
+    std::vector<int32_t> &wprep = plan.wprep;
+    const uint64_t split_pts = plan.split_pts;
+    const uint64_t n_items = items.size();
+    const uint64_t n_prep = prep_list.size();
+    if (split_pts > 0xFFFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu points in large windows)",
+                    (unsigned long long)split_pts);
 
     // ---- layout -------------------------------------------------------------
     const size_t A = 256;
     size_t o_win = 0;
     size_t o_item = align_up(o_win + n_win * sizeof(WinDesc), A);
     size_t o_qd = align_up(o_item + n_items * sizeof(Item), A);
-    size_t desc_bytes = align_up(o_qd + count * sizeof(QDesc), A);
+    size_t o_prep = align_up(o_qd + count * sizeof(QDesc), A);
+    size_t desc_bytes = align_up(o_prep + n_prep * sizeof(uint32_t), A);
     size_t o_sorted = desc_bytes;
-    size_t o_aux = align_up(o_sorted + 2 * n_pts * sizeof(int32_t), A);
+    size_t o_aux = align_up(o_sorted + 2 * split_pts * sizeof(int32_t), A);
     size_t o_acc = align_up(o_aux + n_win * sizeof(WinAux), A);
     size_t o_wdone = align_up(o_acc + n_win * sizeof(unsigned long long), A);
     size_t o_qdone = align_up(o_wdone + n_win * sizeof(uint32_t), A);
@@ -731,56 +757,44 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     WinDesc *hw = reinterpret_cast<WinDesc *>(b->host + o_win);
     Item *hi = reinterpret_cast<Item *>(b->host + o_item);
     QDesc *hq = reinterpret_cast<QDesc *>(b->host + o_qd);
+    uint32_t *hp = reinterpret_cast<uint32_t *>(b->host + o_prep);
     b->h_res = reinterpret_cast<Result *>(b->host + desc_bytes);
-    const bool plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
-    uint32_t w = 0;
-    uint64_t pts = 0;
-    std::vector<Item> items;
-    items.reserve(n_items);
-    if (plain)
-        b->win_first_item.reserve(n_win + 1);
-    for (uint64_t t = 0; t < count; ++t) {
-        uint64_t s3[3];
-        uint32_t m3[3], nw = 0;
-        query_windows(qs[t], ser, t, s3, m3, &nw);
-        hq[t].win0 = w;
+    for (uint64_t i = 0; i < n_win; ++i) {
+        const uint32_t t = wquery[i];
+        WinDesc &d = hw[i];
+        d.x = ser[qs[t].a].d + wstart[i];
+        d.y = ser[qs[t].b].d + wstart[i];
+        d.m = wm[i];
+        d.query = t;
+        d.sorted_off = wsorted[i];
+        d.n_items = wnitems[i];
+    }
+    for (uint64_t t = 0, i = 0; t < count; ++t) {
+        hq[t].win0 = (uint32_t)i;
+        uint32_t nw = 0;
+        while (i < n_win && wquery[i] == (uint32_t)t) {
+            ++nw;
+            ++i;
+        }
         hq[t].nwin = nw;
         hq[t].tau_eff = p->tau_normalize ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
-        for (uint32_t r = 0; r < nw; ++r, ++w) {
-            WinDesc &d = hw[w];
-            d.x = ser[qs[t].a].d + s3[r];
-            d.y = ser[qs[t].b].d + s3[r];
-            d.m = m3[r];
-            d.query = (uint32_t)t;
-            d.sorted_off = (uint32_t)pts;
-            uint32_t ni = std::max<uint32_t>(1, (m3[r] + kItemPoints - 1) / kItemPoints);
-            d.n_items = ni;
-            if (plain)
-                b->win_first_item.push_back((uint32_t)items.size());
-            for (uint32_t it = 0; it < ni; ++it)
-                items.push_back(Item{w, it * kItemPoints});
-            pts += m3[r];
-        }
     }
+    std::copy(prep_list.begin(), prep_list.end(), hp);
     if (plain) {
-        b->win_first_item.push_back((uint32_t)items.size());
+        b->win_first_item = std::move(first_item);
+        b->win_prep = std::move(wprep);
         std::copy(items.begin(), items.end(), hi);
     } else {
-        // largest first (cost = points in the item x window size); a stable
-        // bucket order by log2(cost) is enough for the greedy schedule
-        std::vector<uint32_t> cnt(65, 0);
-        auto bucket = [&](const Item &it) {
-            uint64_t m = hw[it.win].m;
-            uint64_t c = std::min<uint64_t>(kItemPoints, m - it.q0) * m;
-            int lb = 63 - __builtin_clzll(c | 1ull);
-            return 63 - lb;
-        };
-        for (const Item &it : items)
-            cnt[bucket(it) + 1]++;
-        for (int i = 1; i <= 64; ++i)
+        // largest first; a stable bucket order by log2(cost) is enough for
+        // the greedy schedule of the persistent kernel
+        std::vector<uint32_t> cnt(66, 0);
+        auto bucket = [&](uint64_t c) { return 63 - (63 - __builtin_clzll(c | 1ull)); };
+        for (uint64_t i = 0; i < n_items; ++i)
+            cnt[bucket(cost[i]) + 1]++;
+        for (int i = 1; i <= 65; ++i)
             cnt[i] += cnt[i - 1];
-        for (const Item &it : items)
-            hi[cnt[bucket(it)]++] = it;
+        for (uint64_t i = 0; i < n_items; ++i)
+            hi[cnt[bucket(cost[i])]++] = items[i];
     }
 
     // ---- launch arguments -----------------------------------------------------
@@ -799,6 +813,8 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     a.res = reinterpret_cast<Result *>(b->dev + o_res);
     a.psi_d = st->psi_d;
     a.psi_fix = st->psi_fix;
+    a.prep_list = reinterpret_cast<const uint32_t *>(b->dev + o_prep);
+    a.n_prep = (uint32_t)n_prep;
     a.n_win = (uint32_t)n_win;
     a.n_items = (uint32_t)n_items;
     a.n_query = (uint32_t)count;

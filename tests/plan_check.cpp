@@ -1,0 +1,158 @@
+// Host-side check of the batch work list (csrc/wmi_plan.h) on random query
+// mixes: every window covered exactly once, and every item within the limits
+// the main kernel's LDS layout assumes.  Prints OK or the first violation.
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "wmi_plan.h"
+
+using namespace wmi;
+
+static int fail(const char *what, long a, long b)
+{
+    std::printf("FAIL %s (%ld, %ld)\n", what, a, b);
+    return 1;
+}
+
+static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wq, uint64_t count, bool plain)
+{
+    Plan P;
+    plan_items(wm, wq, count, plain, P);
+    const size_t n = wm.size();
+    if (P.items.size() != P.cost.size())
+        return fail("cost size", (long)P.items.size(), (long)P.cost.size());
+    std::vector<int> local_item(n, -1);
+    std::vector<std::vector<uint32_t>> split_q0(n);
+    for (size_t it = 0; it < P.items.size(); ++it) {
+        const Item &I = P.items[it];
+        if (I.info & kItemLocal) {
+            uint32_t nw = I.info & 0xFFu, slots = 0, maxm = 2;
+            if (nw < 1 || nw > (uint32_t)kLocalWindows || (I.info & 0x7FFFFF00u))
+                return fail("local window count", (long)it, (long)nw);
+            if (plain && nw != 1)
+                return fail("plain local item with several windows", (long)it, (long)nw);
+            for (uint32_t r = 0; r < nw; ++r) {
+                uint32_t w = I.win + r;
+                if (w >= n)
+                    return fail("local window out of range", (long)it, (long)w);
+                if (wm[w] > (uint32_t)kLocalSlots)
+                    return fail("large window in a local item", (long)w, (long)wm[w]);
+                if (local_item[w] >= 0)
+                    return fail("window in two local items", (long)w, (long)it);
+                local_item[w] = (int)it;
+                slots += (wm[w] + 1u) & ~1u;
+                maxm = std::max(maxm, wm[w]);
+            }
+            if (slots > (uint32_t)kLocalSlots)
+                return fail("local slots", (long)it, (long)slots);
+            if (nw * plan_pow2(maxm) > (uint32_t)kLocalSort)
+                return fail("local sort entries", (long)it, (long)(nw * plan_pow2(maxm)));
+        } else {
+            if (I.win >= n || wm[I.win] <= (uint32_t)kLocalSlots)
+                return fail("split item of a small window", (long)it, (long)I.win);
+            if (I.info % kSplitPoints || I.info >= wm[I.win])
+                return fail("split first point", (long)it, (long)I.info);
+            split_q0[I.win].push_back(I.info);
+        }
+    }
+    uint64_t pts = 0;
+    size_t pi = 0;
+    for (size_t w = 0; w < n; ++w) {
+        if (wm[w] > (uint32_t)kLocalSlots) {
+            uint32_t ni = (wm[w] + kSplitPoints - 1) / kSplitPoints;
+            if (split_q0[w].size() != ni || P.wnitems[w] != ni)
+                return fail("split coverage", (long)w, (long)split_q0[w].size());
+            std::vector<bool> seen(ni, false);
+            for (uint32_t q0 : split_q0[w]) {
+                if (seen[q0 / kSplitPoints])
+                    return fail("split block twice", (long)w, (long)q0);
+                seen[q0 / kSplitPoints] = true;
+            }
+            if (pi >= P.prep_list.size() || P.prep_list[pi] != w)
+                return fail("prep list", (long)w, (long)pi);
+            if (P.wsorted[w] != pts)
+                return fail("sorted offset", (long)w, (long)P.wsorted[w]);
+            if (plain && P.wprep[w] != (int32_t)pi)
+                return fail("plain prep index", (long)w, (long)P.wprep[w]);
+            pts += wm[w];
+            ++pi;
+        } else if (local_item[w] < 0) {
+            return fail("window not covered", (long)w, (long)wm[w]);
+        }
+    }
+    if (pi != P.prep_list.size() || pts != P.split_pts)
+        return fail("prep totals", (long)pi, (long)pts);
+    if (!plain) {
+        // a query whose windows are all local and fit one item is not cut
+        size_t w = 0;
+        for (uint64_t t = 0; t < count; ++t) {
+            size_t w0 = w;
+            while (w < n && wq[w] == t)
+                ++w;
+            uint32_t slots = 0, maxm = 2, nw = (uint32_t)(w - w0);
+            bool local = true;
+            for (size_t r = w0; r < w; ++r) {
+                local = local && wm[r] <= (uint32_t)kLocalSlots;
+                slots += (wm[r] + 1u) & ~1u;
+                maxm = std::max(maxm, wm[r]);
+            }
+            bool fits = local && nw <= (uint32_t)kLocalWindows && slots <= (uint32_t)kLocalSlots &&
+                        nw * plan_pow2(maxm) <= (uint32_t)kLocalSort;
+            if (fits)
+                for (size_t r = w0 + 1; r < w; ++r)
+                    if (local_item[r] != local_item[w0])
+                        return fail("query cut across items", (long)t, (long)r);
+        }
+    } else {
+        if (P.first_item.size() != n + 1)
+            return fail("plain first_item size", (long)P.first_item.size(), (long)n);
+        for (size_t w = 0; w < n; ++w)
+            for (uint32_t it = P.first_item[w]; it < P.first_item[w + 1]; ++it)
+                if (P.items[it].win != w)
+                    return fail("plain items of another window", (long)w, (long)it);
+    }
+    return 0;
+}
+
+int main(int argc, char **argv)
+{
+    int cases = argc > 1 ? std::atoi(argv[1]) : 300;
+    std::mt19937_64 rng(12345);
+    for (int c = 0; c < cases; ++c) {
+        std::vector<uint32_t> wm, wq;
+        uint64_t count = 1 + rng() % 400;
+        int style = (int)(rng() % 4);
+        for (uint64_t t = 0; t < count; ++t) {
+            auto draw = [&]() -> uint32_t {
+                switch (style) {
+                case 0: return (uint32_t)(1 + rng() % 4096);
+                case 1: return (uint32_t)(1u << (5 + rng() % 8));   // 32..4096
+                case 2: return (uint32_t)(1 + rng() % 600);
+                default: return (uint32_t)(1 + rng() % 64);
+                }
+            };
+            if (rng() % 3 == 0) {  // a noise triple: base, extension, union
+                uint32_t base = draw(), ext = 1 + (uint32_t)(rng() % 300);
+                if (base + ext > 4096)
+                    base = 4096 - ext;
+                wm.push_back(base);
+                wm.push_back(ext);
+                wm.push_back(base + ext);
+                for (int r = 0; r < 3; ++r)
+                    wq.push_back((uint32_t)t);
+            } else {
+                wm.push_back(draw());
+                wq.push_back((uint32_t)t);
+            }
+        }
+        for (int plain = 0; plain < 2; ++plain)
+            if (check(wm, wq, count, plain != 0)) {
+                std::printf("case %d style %d plain %d\n", c, style, plain);
+                return 1;
+            }
+    }
+    std::printf("OK %d\n", cases);
+    return 0;
+}
