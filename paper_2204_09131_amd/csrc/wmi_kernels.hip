@@ -762,7 +762,8 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             for (uint32_t t = tid; t < npairs; t += kBlock) {
                 const uint32_t lo = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u));
                 const uint32_t hi = lo + stride;
-                const bool asc = (lo & size) == 0u;
+                // direction from the index inside the segment: every segment ascends
+                const bool asc = ((lo & (P - 1u)) & size) == 0u;
                 int32_t a0 = srt_x[lo], a1 = srt_x[hi];
                 if ((a0 > a1) == asc) {
                     srt_x[lo] = a1;
