@@ -341,11 +341,12 @@ def test_budget(wmi):
     with wmi.Store(0, budget_bytes=1 << 20) as st:
         x, y = synth.relation("linear", 5000, 1)
         a, b = st.add_series(x), st.add_series(y)
-        q = synth.make_queries(a, b, np.arange(0, 4000, 1), 512)
+        # about 130 bytes of device memory per single-window query
+        q = synth.make_queries(a, b, np.tile(np.arange(0, 4000, 1), 5), 64)   # ~2.5 MiB
         with pytest.raises(wmi.WmiError) as e:
             st.submit(q, k=4)
         assert e.value.code == wmi.WMI_ENOMEM
-        small = synth.make_queries(a, b, np.arange(0, 300, 1), 256)  # ~0.65 MiB: two do not fit
+        small = synth.make_queries(a, b, np.arange(0, 4500, 1) % 4000, 64)   # ~0.6 MiB: two do not fit
         b1 = st.submit(small, k=4)
         try:
             b2 = st.submit(small, k=4, nonblocking=True)
