@@ -123,6 +123,10 @@ typedef struct {
     uint64_t ordered_pairs;  /* sum of m (m - 1) over those windows            */
     uint64_t launches;       /* kernel launches used                           */
     double device_ms;        /* event time from first to last launch           */
+    uint32_t items;          /* work items of the main kernel                  */
+    uint32_t grid;           /* workgroups of the persistent main kernel       */
+    uint32_t wg_per_cu;      /* resident main-kernel workgroups per CU         */
+    uint32_t cus;            /* compute units of the device                    */
 } wmi_batch_stats;
 
 /* Library version as (major << 16) | minor. */

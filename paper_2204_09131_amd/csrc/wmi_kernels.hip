@@ -365,120 +365,205 @@ __device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, i
 // split items: one block of up to 512 query points of a large window
 // --------------------------------------------------------------------------
 
-// 32-bit keys.  Lane query i = q0 + tid + q * kBlock.
+constexpr int kChunk = 2048;  // candidates (and sorted-marginal entries) staged in LDS at a time
+
+// (X - min) << nb for point i of a window: a 32-bit key coordinate (nb > 0)
+// or the offset grid integer (nb == 0, 64-bit key path).
+__device__ __forceinline__ uint32_t key_coord(const float *v, int i, int32_t mn, uint32_t nb)
+{
+    uint32_t off = 0;
+    return (uint32_t)(grid_int(v[i], off) - mn) << nb;
+}
+
+// Scan candidates [c0, c0 + cn) staged in LDS with 32-bit keys.
 template <int K, int Q>
-__device__ __forceinline__ void split_knn_narrow(const uint32_t *__restrict__ cand, int m, uint32_t nb, int q0,
-                                                 int tid, uint32_t est, uint32_t (&rx)[Q], uint32_t (&ry)[Q])
+__device__ __forceinline__ void scan_narrow(const uint32_t *__restrict__ cand, int c0, int cn,
+                                            const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
+                                            uint32_t (&top)[Q][K + 1])
 {
     constexpr int S = K + 1;
-    uint32_t qx[Q], qy[Q];
-    uint32_t top[Q][S];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        int i = min(q0 + tid + q * kBlock, m - 1);
-        qx[q] = cand[2 * i];
-        qy[q] = cand[2 * i + 1];
-#pragma unroll
-        for (int r = 0; r < S; ++r)
-            top[q][r] = 0xFFFFFFFFu;
-    }
     const uint4 *c4 = reinterpret_cast<const uint4 *>(cand);
     int j = 0;
-    for (; j + 1 < m; j += 2) {
+    for (; j + 1 < cn; j += 2) {
         uint4 c = c4[j >> 1];
+        const uint32_t j0 = (uint32_t)(c0 + j);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            uint32_t k0 = tmax(sad_key(qx[q], c.x, (uint32_t)j), sad_key(qy[q], c.y, (uint32_t)j));
+            uint32_t k0 = tmax(sad_key(qx[q], c.x, j0), sad_key(qy[q], c.y, j0));
             insert_sorted<S>(top[q], k0);
-            uint32_t k1 = tmax(sad_key(qx[q], c.z, (uint32_t)j + 1u), sad_key(qy[q], c.w, (uint32_t)j + 1u));
+            uint32_t k1 = tmax(sad_key(qx[q], c.z, j0 + 1u), sad_key(qy[q], c.w, j0 + 1u));
             insert_sorted<S>(top[q], k1);
         }
     }
-    if (j < m) {
-        uint32_t cx = cand[2 * j], cy = cand[2 * j + 1];
+    if (j < cn) {
+        const uint32_t cx = cand[2 * j], cy = cand[2 * j + 1], j0 = (uint32_t)(c0 + j);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            insert_sorted<S>(top[q], tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j)));
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        uint32_t self = (uint32_t)min(q0 + tid + q * kBlock, m - 1);
-        radii_from_keys<K, uint32_t>(top[q], self, (int)nb, (1u << nb) - 1u, m, cand, 0u, qx[q], qy[q], (int)nb, est,
-                                     rx[q], ry[q]);
+            insert_sorted<S>(top[q], tmax(sad_key(qx[q], cx, j0), sad_key(qy[q], cy, j0)));
     }
 }
 
-// 64-bit keys (d << 12 | j); the staged values are X - min.
+// Same with 64-bit keys (d << 12 | j) over offset grid integers.
 template <int K, int Q>
-__device__ __forceinline__ void split_knn_wide(const uint32_t *__restrict__ cand, int m, int q0, int tid,
-                                               uint32_t est, uint32_t (&rx)[Q], uint32_t (&ry)[Q])
+__device__ __forceinline__ void scan_wide(const uint32_t *__restrict__ cand, int c0, int cn,
+                                          const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
+                                          unsigned long long (&top)[Q][K + 1])
 {
     constexpr int S = K + 1;
-    uint32_t qx[Q], qy[Q];
-    unsigned long long top[Q][S];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        int i = min(q0 + tid + q * kBlock, m - 1);
-        qx[q] = cand[2 * i];
-        qy[q] = cand[2 * i + 1];
-#pragma unroll
-        for (int r = 0; r < S; ++r)
-            top[q][r] = ~0ull;
-    }
-    for (int j = 0; j < m; ++j) {
-        uint32_t cx = cand[2 * j], cy = cand[2 * j + 1];
+    for (int j = 0; j < cn; ++j) {
+        const uint32_t cx = cand[2 * j], cy = cand[2 * j + 1];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             uint32_t d = tmax(sad_u32(qx[q], cx, 0u), sad_u32(qy[q], cy, 0u));
-            unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
+            unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)(c0 + j);
             if (key < top[q][S - 1])
                 insert_sorted<S>(top[q], key);
         }
     }
+}
+
+// Radii of a query from its k+1 smallest keys; neighbour coordinates are
+// re-read from the series (k loads per dimension).
+template <int K, typename T>
+__device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int shift, uint32_t mask,
+                                            const WinDesc &d, const WinAux &ax, uint32_t qx, uint32_t qy,
+                                            uint32_t est, uint32_t &rx, uint32_t &ry)
+{
+    const uint32_t nb = ax.nb;
+    T nbk[K];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        unsigned long long self = (unsigned long long)min(q0 + tid + q * kBlock, m - 1);
-        radii_from_keys<K, unsigned long long>(top[q], self, 12, 0xFFFu, m, cand, 0u, qx[q], qy[q], 0, est, rx[q],
-                                               ry[q]);
+    for (int r = 0; r < K; ++r)
+        nbk[r] = top[r] < self ? top[r] : top[r + 1];
+    if (est == 0) {
+        uint32_t ex = 0, ey = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int jj = (int)min((uint32_t)(nbk[r] & (T)mask), d.m - 1u);
+            ex = tmax(ex, sad_u32(qx, key_coord(d.x, jj, ax.min_x, nb), 0u) >> nb);
+            ey = tmax(ey, sad_u32(qy, key_coord(d.y, jj, ax.min_y, nb), 0u) >> nb);
+        }
+        rx = ex;
+        ry = ey;
+    } else {
+        rx = (uint32_t)(nbk[K - 1] >> shift);
+        ry = rx;
     }
 }
 
 template <int K, int Q>
 __device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDesc &d, const WinAux &ax, int q0,
-                                                uint32_t *cand)
+                                                uint32_t *buf)
 {
+    constexpr int S = K + 1;
     const int m = (int)d.m;
     const int tid = threadIdx.x;
-    uint32_t rx[Q], ry[Q];
-    if (ax.nb)
-        split_knn_narrow<K, Q>(cand, m, ax.nb, q0, tid, a.estimator, rx, ry);
-    else
-        split_knn_wide<K, Q>(cand, m, q0, tid, a.estimator, rx, ry);
-    int32_t xi[Q], yi[Q];
+    const uint32_t nb = ax.nb;
+    uint32_t qx[Q], qy[Q], rx[Q], ry[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        int i = min(q0 + tid + q * kBlock, m - 1);
-        xi[q] = (int32_t)(cand[2 * i] >> ax.nb) + ax.min_x;
-        yi[q] = (int32_t)(cand[2 * i + 1] >> ax.nb) + ax.min_y;
+        const int i = min(q0 + tid + q * kBlock, m - 1);
+        qx[q] = key_coord(d.x, i, ax.min_x, nb);
+        qy[q] = key_coord(d.y, i, ax.min_y, nb);
     }
-    __syncthreads();
-    // the sorted marginals replace the candidates in LDS
-    int32_t *sx = reinterpret_cast<int32_t *>(cand);
-    int32_t *sy = sx + kMaxWindow;
+    // ---- neighbours: candidates stream through LDS in chunks
+    if (nb) {
+        uint32_t top[Q][S];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                top[q][r] = 0xFFFFFFFFu;
+        for (int c0 = 0; c0 < m; c0 += kChunk) {
+            const int cn = min(kChunk, m - c0);
+            __syncthreads();
+            for (int i = tid; i < cn; i += kBlock) {
+                buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, nb);
+                buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, nb);
+            }
+            __syncthreads();
+            scan_narrow<K, Q>(buf, c0, cn, qx, qy, top);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            split_radii<K, uint32_t>(top[q], (uint32_t)min(q0 + tid + q * kBlock, m - 1), (int)nb,
+                                     (1u << nb) - 1u, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
+    } else {
+        unsigned long long top[Q][S];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                top[q][r] = ~0ull;
+        for (int c0 = 0; c0 < m; c0 += kChunk) {
+            const int cn = min(kChunk, m - c0);
+            __syncthreads();
+            for (int i = tid; i < cn; i += kBlock) {
+                buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, 0u);
+                buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, 0u);
+            }
+            __syncthreads();
+            scan_wide<K, Q>(buf, c0, cn, qx, qy, top);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            split_radii<K, unsigned long long>(top[q], (unsigned long long)min(q0 + tid + q * kBlock, m - 1), 12,
+                                               0xFFFu, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
+    }
+    // ---- marginal counts over the sorted marginals, chunk by chunk
+    int32_t xi[Q], yi[Q];
+    int hx[Q], lx[Q], hy[Q], ly[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        xi[q] = (int32_t)(qx[q] >> nb) + ax.min_x;
+        yi[q] = (int32_t)(qy[q] >> nb) + ax.min_y;
+        hx[q] = lx[q] = hy[q] = ly[q] = 0;
+    }
     const int32_t *src = a.sorted + 2ull * d.sorted_off;
-    for (int i = tid; i < m; i += kBlock) {
-        sx[i] = src[i];
-        sy[i] = src[m + i];
+    int32_t *sx = reinterpret_cast<int32_t *>(buf);
+    int32_t *sy = sx + kChunk;
+    const bool strict = a.estimator != 0;
+    for (int c0 = 0; c0 < m; c0 += kChunk) {
+        const int cn = min(kChunk, m - c0);
+        __syncthreads();
+        for (int i = tid; i < cn; i += kBlock) {
+            sx[i] = src[c0 + i];
+            sy[i] = src[m + c0 + i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int32_t ex = (int32_t)rx[q], ey = (int32_t)ry[q];
+            // estimator 0: #{<= x+e} - #{< x-e};  estimator 1: #{< x+e} - #{<= x-e}
+            if (strict) {
+                hx[q] += count_lt(sx, cn, xi[q] + ex);
+                lx[q] += count_le(sx, cn, xi[q] - ex);
+                hy[q] += count_lt(sy, cn, yi[q] + ey);
+                ly[q] += count_le(sy, cn, yi[q] - ey);
+            } else {
+                hx[q] += count_le(sx, cn, xi[q] + ex);
+                lx[q] += count_lt(sx, cn, xi[q] - ex);
+                hy[q] += count_le(sy, cn, yi[q] + ey);
+                ly[q] += count_lt(sy, cn, yi[q] - ey);
+            }
+        }
     }
-    __syncthreads();
     long long part = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        int i = q0 + tid + q * kBlock;
+        const int i = q0 + tid + q * kBlock;
         if (i >= m)
             continue;
         int cx, cy;
-        part += count_terms(a, sx, sy, m, xi[q], yi[q], (int32_t)rx[q], (int32_t)ry[q], cx, cy);
+        if (!strict) {
+            cx = hx[q] - lx[q] - 1;
+            cy = hy[q] - ly[q] - 1;
+            part += a.psi_fix[cx] + a.psi_fix[cy];
+        } else {
+            // a zero joint radius counts nothing; otherwise the point itself is inside
+            cx = rx[q] > 0 ? hx[q] - lx[q] - 1 : 0;
+            cy = rx[q] > 0 ? hy[q] - ly[q] - 1 : 0;
+            part += a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
+        }
         if (a.dbg_nx) {
             a.dbg_nx[i] = (uint32_t)cx;
             a.dbg_ny[i] = (uint32_t)cy;
@@ -490,7 +575,7 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDe
 }
 
 template <int K>
-__device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *cand, long long *s_part)
+__device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *buf, long long *s_part)
 {
     const WinDesc d = a.win[w];
     const WinAux ax = a.aux[w];
@@ -498,19 +583,10 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *ca
     const int tid = threadIdx.x;
     long long part = 0;
     if (m > K) {
-        // stage the window: 32-bit keys, or X - min for the 64-bit path
-        uint32_t off = 0;
-        for (int i = tid; i < m; i += kBlock) {
-            int32_t xi = grid_int(d.x[i], off);
-            int32_t yi = grid_int(d.y[i], off);
-            cand[2 * i] = (uint32_t)(xi - ax.min_x) << ax.nb;
-            cand[2 * i + 1] = (uint32_t)(yi - ax.min_y) << ax.nb;
-        }
-        __syncthreads();
         if (m - q0 <= kBlock)
-            part = split_body<K, 1>(a, d, ax, q0, cand);
+            part = split_body<K, 1>(a, d, ax, q0, buf);
         else
-            part = split_body<K, 2>(a, d, ax, q0, cand);
+            part = split_body<K, 2>(a, d, ax, q0, buf);
     }
     // workgroup sum of the fixed-point terms (exact, order-free)
     for (int o = 32; o > 0; o >>= 1)
@@ -522,10 +598,8 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *ca
         long long tot = 0;
         for (int wv = 0; wv < kBlock / 64; ++wv)
             tot += s_part[wv];
-        unsigned long long seen = 0;
         if (m > K)
-            seen = atomicAdd(&a.acc[w], (unsigned long long)tot);
-        (void)seen;
+            atomicAdd(&a.acc[w], (unsigned long long)tot);
         wait_returned();
         uint32_t prev = atomicAdd(&a.wdone[w], 1u);
         if (prev + 1u == d.n_items) {
@@ -837,7 +911,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 template <int K>
 __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
 {
-    __shared__ __align__(16) uint32_t buf[2 * kMaxWindow];
+    __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
     __shared__ long long s_part[kBlock / 64];
     __shared__ uint32_t s_item;

@@ -827,6 +827,10 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     int occ = main_occupancy(p->k);
     uint64_t slots = (uint64_t)st->cu_count * (uint64_t)occ;
     b->grid = (uint32_t)std::min<uint64_t>(n_items, slots);
+    b->stats.items = (uint32_t)n_items;
+    b->stats.grid = b->grid;
+    b->stats.wg_per_cu = (uint32_t)occ;
+    b->stats.cus = (uint32_t)st->cu_count;
 
     {
         std::lock_guard<std::mutex> lk(st->mu);

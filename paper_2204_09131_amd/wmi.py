@@ -72,7 +72,9 @@ class _Timing(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("windows", ctypes.c_uint64), ("ordered_pairs", ctypes.c_uint64),
-                ("launches", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
+                ("launches", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("items", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("cus", ctypes.c_uint32)]
 
 
 _lib = None
@@ -186,7 +188,8 @@ class Batch:
         s = _Stats()
         _check(lib().wmi_batch_stats_get(self.h, ctypes.byref(s)))
         return {"windows": s.windows, "ordered_pairs": s.ordered_pairs, "launches": s.launches,
-                "device_ms": s.device_ms}
+                "device_ms": s.device_ms, "items": s.items, "grid": s.grid, "wg_per_cu": s.wg_per_cu,
+                "cus": s.cus}
 
     def destroy(self):
         if self.h:
