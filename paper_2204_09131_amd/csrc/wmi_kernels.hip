@@ -933,18 +933,16 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
         }
         if (it >= a.n_items)
             break;
-        // fetch the next item now; its latency overlaps this item's work
-        uint32_t next = 0;
-        if (a.persistent && tid == 0)
-            next = atomicAdd(a.counter, 1u);
         const Item itm = a.item[a.item_begin + it];
         if (itm.info & kItemLocal)
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
         else
             split_item<K>(a, itm.win, (int)itm.info, buf, s_part);
         __syncthreads();
+        // take the next item only now: a workgroup still busy must not hold
+        // one (items are largest first); other workgroups keep the CU busy
         if (a.persistent && tid == 0)
-            s_item = next;
+            s_item = atomicAdd(a.counter, 1u);
         __syncthreads();
     }
 }
