@@ -934,10 +934,16 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
         if (it >= a.n_items)
             break;
         const Item itm = a.item[a.item_begin + it];
-        if (itm.info & kItemLocal)
+        if (itm.info & kItemLocal) {
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
-        else
+        } else {
+            // split items are the largest, taken first: let their waves issue
+            // ahead of the short local items sharing the CU, so they are not
+            // the last to finish
+            __builtin_amdgcn_s_setprio(2);
             split_item<K>(a, itm.win, (int)itm.info, buf, s_part);
+            __builtin_amdgcn_s_setprio(0);
+        }
         __syncthreads();
         // take the next item only now: a workgroup still busy must not hold
         // one (items are largest first); other workgroups keep the CU busy
