@@ -375,31 +375,54 @@ __device__ __forceinline__ uint32_t key_coord(const float *v, int i, int32_t mn,
     return (uint32_t)(grid_int(v[i], off) - mn) << nb;
 }
 
-// Scan candidates [c0, c0 + cn) staged in LDS with 32-bit keys.
-template <int K, int Q>
-__device__ __forceinline__ void scan_narrow(const uint32_t *__restrict__ cand, int c0, int cn,
-                                            const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
-                                            uint32_t (&top)[Q][K + 1])
+// Scan candidates [jlo, jhi) (global indices; LDS holds [c0, c0 + chunk))
+// with 32-bit keys into k-entry lists.  Slot MQ (if >= 0) is the one whose
+// own point can appear in this range: its key for j == self is replaced by
+// the largest key, so the point never enters its own list.
+template <int K, int Q, int MQ>
+__device__ __forceinline__ void scan_seg(const uint32_t *__restrict__ cand, int c0, int jlo, int jhi,
+                                         const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
+                                         const uint32_t (&self)[Q], uint32_t (&top)[Q][K])
 {
-    constexpr int S = K + 1;
+    if (jlo >= jhi)
+        return;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(cand);
-    int j = 0;
-    for (; j + 1 < cn; j += 2) {
-        uint4 c = c4[j >> 1];
-        const uint32_t j0 = (uint32_t)(c0 + j);
+    int j = jlo;
+    if ((j - c0) & 1) {  // keep 16-byte reads aligned (segment starts are even in practice)
+        const uint32_t cx = cand[2 * (j - c0)], cy = cand[2 * (j - c0) + 1];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            uint32_t k0 = tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j));
+            if (q == MQ)
+                k0 = (uint32_t)j == self[q] ? 0xFFFFFFFFu : k0;
+            insert_sorted<K>(top[q], k0);
+        }
+        ++j;
+    }
+    for (; j + 1 < jhi; j += 2) {
+        uint4 c = c4[(j - c0) >> 1];
+        const uint32_t j0 = (uint32_t)j;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             uint32_t k0 = tmax(sad_key(qx[q], c.x, j0), sad_key(qy[q], c.y, j0));
-            insert_sorted<S>(top[q], k0);
             uint32_t k1 = tmax(sad_key(qx[q], c.z, j0 + 1u), sad_key(qy[q], c.w, j0 + 1u));
-            insert_sorted<S>(top[q], k1);
+            if (q == MQ) {
+                k0 = j0 == self[q] ? 0xFFFFFFFFu : k0;
+                k1 = j0 + 1u == self[q] ? 0xFFFFFFFFu : k1;
+            }
+            insert_sorted<K>(top[q], k0);
+            insert_sorted<K>(top[q], k1);
         }
     }
-    if (j < cn) {
-        const uint32_t cx = cand[2 * j], cy = cand[2 * j + 1], j0 = (uint32_t)(c0 + j);
+    if (j < jhi) {
+        const uint32_t cx = cand[2 * (j - c0)], cy = cand[2 * (j - c0) + 1];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            insert_sorted<S>(top[q], tmax(sad_key(qx[q], cx, j0), sad_key(qy[q], cy, j0)));
+        for (int q = 0; q < Q; ++q) {
+            uint32_t k0 = tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j));
+            if (q == MQ)
+                k0 = (uint32_t)j == self[q] ? 0xFFFFFFFFu : k0;
+            insert_sorted<K>(top[q], k0);
+        }
     }
 }
 
@@ -422,18 +445,14 @@ __device__ __forceinline__ void scan_wide(const uint32_t *__restrict__ cand, int
     }
 }
 
-// Radii of a query from its k+1 smallest keys; neighbour coordinates are
-// re-read from the series (k loads per dimension).
+// Radii of a query from the keys of its k neighbours; neighbour coordinates
+// are re-read from the series (k loads per dimension).
 template <int K, typename T>
-__device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int shift, uint32_t mask,
-                                            const WinDesc &d, const WinAux &ax, uint32_t qx, uint32_t qy,
-                                            uint32_t est, uint32_t &rx, uint32_t &ry)
+__device__ __forceinline__ void split_radii_k(const T (&nbk)[K], int shift, uint32_t mask, const WinDesc &d,
+                                              const WinAux &ax, uint32_t qx, uint32_t qy, uint32_t est,
+                                              uint32_t &rx, uint32_t &ry)
 {
     const uint32_t nb = ax.nb;
-    T nbk[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r)
-        nbk[r] = top[r] < self ? top[r] : top[r + 1];
     if (est == 0) {
         uint32_t ex = 0, ey = 0;
 #pragma unroll
@@ -448,6 +467,19 @@ __device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int s
         rx = (uint32_t)(nbk[K - 1] >> shift);
         ry = rx;
     }
+}
+
+// Same from the k+1 smallest keys of a scan that included the point itself.
+template <int K, typename T>
+__device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int shift, uint32_t mask,
+                                            const WinDesc &d, const WinAux &ax, uint32_t qx, uint32_t qy,
+                                            uint32_t est, uint32_t &rx, uint32_t &ry)
+{
+    T nbk[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        nbk[r] = top[r] < self ? top[r] : top[r + 1];
+    split_radii_k<K, T>(nbk, shift, mask, d, ax, qx, qy, est, rx, ry);
 }
 
 template <int K, int Q>
@@ -467,26 +499,40 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDe
     }
     // ---- neighbours: candidates stream through LDS in chunks
     if (nb) {
-        uint32_t top[Q][S];
+        // k-entry lists; the point itself is masked inside its wave's band of
+        // 64 consecutive candidates (queries of a wave are consecutive points)
+        uint32_t top[Q][K], self[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q) {
+            self[q] = (uint32_t)(q0 + tid + q * kBlock);
 #pragma unroll
-            for (int r = 0; r < S; ++r)
+            for (int r = 0; r < K; ++r)
                 top[q][r] = 0xFFFFFFFFu;
+        }
+        const int band0 = __builtin_amdgcn_readfirstlane(q0 + (tid & ~63));  // wave-uniform
+        const int band1 = band0 + kBlock;
         for (int c0 = 0; c0 < m; c0 += kChunk) {
-            const int cn = min(kChunk, m - c0);
+            const int cn = min(kChunk, m - c0), e = c0 + cn;
             __syncthreads();
             for (int i = tid; i < cn; i += kBlock) {
                 buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, nb);
                 buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, nb);
             }
             __syncthreads();
-            scan_narrow<K, Q>(buf, c0, cn, qx, qy, top);
+            scan_seg<K, Q, -1>(buf, c0, c0, min(e, band0), qx, qy, self, top);
+            scan_seg<K, Q, 0>(buf, c0, max(c0, band0), min(e, band0 + 64), qx, qy, self, top);
+            if (Q == 1) {
+                scan_seg<K, Q, -1>(buf, c0, max(c0, band0 + 64), e, qx, qy, self, top);
+            } else {
+                scan_seg<K, Q, -1>(buf, c0, max(c0, band0 + 64), min(e, band1), qx, qy, self, top);
+                scan_seg<K, Q, (Q > 1 ? 1 : -1)>(buf, c0, max(c0, band1), min(e, band1 + 64), qx, qy, self, top);
+                scan_seg<K, Q, -1>(buf, c0, max(c0, band1 + 64), e, qx, qy, self, top);
+            }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            split_radii<K, uint32_t>(top[q], (uint32_t)min(q0 + tid + q * kBlock, m - 1), (int)nb,
-                                     (1u << nb) - 1u, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
+            split_radii_k<K, uint32_t>(top[q], (int)nb, (1u << nb) - 1u, d, ax, qx[q], qy[q], a.estimator, rx[q],
+                                       ry[q]);
     } else {
         unsigned long long top[Q][S];
 #pragma unroll
@@ -824,7 +870,9 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             m_min = min(m_min, __shfl_xor(m_min, o, 64));
             nb_min = min(nb_min, (uint32_t)__shfl_xor((int)nb_min, o, 64));
         }
-        const int mode = nb_min == 0u ? 2 : (m_max == m_min ? 0 : 1);
+        // the reductions leave the same value in every lane: make that explicit
+        m_max = __builtin_amdgcn_readfirstlane(m_max);
+        const int mode = __builtin_amdgcn_readfirstlane(nb_min == 0u ? 2 : (m_max == m_min ? 0 : 1));
         local_knn<K>(cand, L.off[wl], m, il, nb, mode, m_max, a.estimator, RX[q], RY[q]);
     }
     __syncthreads();
