@@ -7,8 +7,10 @@
 //                        a local item is up to kLocalWindows consecutive
 //                        windows (whole queries where they fit) done entirely
 //                        inside one workgroup
-//   u32      prep[Np]    the split windows (their marginals are sorted by the
-//                        prep kernel; local items sort in LDS)
+//   u32      prep[Np]    the split windows; their marginals are sorted by prep
+//                        items at the head of the queue (plain form: by the
+//                        prep kernel); local items sort in LDS
+//   u32      ready[W]    per window: sorted marginals written
 //   QDesc    qd[Qn]      one per query: its first window, window count, tau
 //   int32    sorted[2*P] per window, its x and y grid integers in ascending
 //                        order (P = sum of m); written by the prep kernel
@@ -35,6 +37,9 @@ constexpr int kLocalSlots = 2 * kBlock;   // points (each window padded to even)
 constexpr int kLocalWindows = 16;         // windows per local item
 constexpr int kLocalSort = 1024;          // windows x pow2(max m) per local item
 constexpr uint32_t kItemLocal = 0x80000000u;
+constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
+constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
+constexpr uint32_t kErrWait = 1u;            // error word: a dependency wait gave up
 
 struct WinDesc {            // 32 bytes
     const float *x;         // series a + window start
@@ -46,8 +51,8 @@ struct WinDesc {            // 32 bytes
 };
 
 struct Item {               // 8 bytes
-    uint32_t win;           // split: the window; local: its first window
-    uint32_t info;          // split: first query point; local: kItemLocal | windows
+    uint32_t win;           // split / prep: the window; local: its first window
+    uint32_t info;          // split: first query point; local: kItemLocal | windows; prep: kItemPrep
 };
 
 struct QDesc {              // 16 bytes
@@ -92,6 +97,8 @@ struct LaunchArgs {
     uint32_t win_begin;           // prep kernel: first entry of prep_list for this launch
     const uint32_t *prep_list;    // windows the prep kernel sorts (split windows)
     uint32_t n_prep;
+    uint32_t *ready;              // per window: its sorted marginals are in HBM
+    uint32_t *err;                // error word (kErrWait)
     // debug export (one window): per point counts and radii, or null
     uint32_t *dbg_nx, *dbg_ny;
     float *dbg_ex, *dbg_ey;

@@ -128,7 +128,10 @@ __global__ void clear_kernel(LaunchArgs a)
     for (uint32_t w = t; w < a.n_win; w += stride) {
         a.acc[w] = 0ull;
         a.wdone[w] = 0u;
+        a.ready[w] = 0u;
     }
+    if (t == 0)
+        a.err[0] = 0u;
     for (uint32_t q = t; q < a.n_query; q += stride)
         a.qdone[q] = 0u;
     if (t == 0)
@@ -136,99 +139,55 @@ __global__ void clear_kernel(LaunchArgs a)
 }
 
 // --------------------------------------------------------------------------
-// prep: grid integers, minima, grid check, sorted marginals (one WG / window)
+// prep: sorted marginals of a split window (one workgroup)
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
-{
-    __shared__ int32_t sx[kMaxWindow];
-    __shared__ int32_t sy[kMaxWindow];
-    __shared__ int32_t s_red[5];
 
-    const uint32_t pi = a.win_begin + blockIdx.x;
-    if (pi >= a.n_prep)
-        return;
-    const uint32_t w = a.prep_list[pi];
-    const WinDesc d = a.win[w];
-    const int m = (int)d.m;
+// Sort the grid integers of one coordinate of a window into out[0..m),
+// bitonic in LDS (P = next power of two >= m entries of scratch).
+__device__ void sort_marginal(const float *v, int m, int32_t *scratch, int32_t *out)
+{
     const int tid = threadIdx.x;
     int P = 1;
     while (P < m)
         P <<= 1;
-
-    if (tid == 0) {
-        s_red[0] = INT32_MAX;
-        s_red[1] = INT32_MIN;
-        s_red[2] = INT32_MAX;
-        s_red[3] = INT32_MIN;
-        s_red[4] = 0;
-    }
-    __syncthreads();
-
-    int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
     uint32_t off = 0;
-    for (int i = tid; i < P; i += kBlock) {
-        if (i < m) {
-            int32_t xi = grid_int(d.x[i], off);
-            int32_t yi = grid_int(d.y[i], off);
-            sx[i] = xi;
-            sy[i] = yi;
-            mnx = min(mnx, xi);
-            mxx = max(mxx, xi);
-            mny = min(mny, yi);
-            mxy = max(mxy, yi);
-        } else {
-            sx[i] = INT32_MAX;
-            sy[i] = INT32_MAX;
-        }
-    }
-    atomicMin(&s_red[0], mnx);
-    atomicMax(&s_red[1], mxx);
-    atomicMin(&s_red[2], mny);
-    atomicMax(&s_red[3], mxy);
-    if (off)
-        atomicOr(&s_red[4], 1);
-
-    // bitonic sort of both marginals, P = next power of two >= m
+    for (int i = tid; i < P; i += kBlock)
+        scratch[i] = i < m ? grid_int(v[i], off) : INT32_MAX;
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
             for (int t = tid; t < (P >> 1); t += kBlock) {
-                int lo = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
-                int hi = lo + stride;
-                bool asc = (lo & size) == 0;
-                int32_t a0 = sx[lo], a1 = sx[hi];
+                const int lo = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const int32_t a0 = scratch[lo], a1 = scratch[hi];
                 if ((a0 > a1) == asc) {
-                    sx[lo] = a1;
-                    sx[hi] = a0;
-                }
-                int32_t b0 = sy[lo], b1 = sy[hi];
-                if ((b0 > b1) == asc) {
-                    sy[lo] = b1;
-                    sy[hi] = b0;
+                    scratch[lo] = a1;
+                    scratch[hi] = a0;
                 }
             }
         }
     }
     __syncthreads();
+    for (int i = tid; i < m; i += kBlock)
+        out[i] = scratch[i];
+    __syncthreads();
+}
 
+// Write the sorted marginals of window w to HBM, make them visible to every
+// CU, then raise the window's ready flag.
+__device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf)
+{
+    const WinDesc d = a.win[w];
+    const int m = (int)d.m;
     int32_t *out = a.sorted + 2ull * d.sorted_off;
-    for (int i = tid; i < m; i += kBlock) {
-        out[i] = sx[i];
-        out[m + i] = sy[i];
-    }
-    if (tid == 0) {
-        WinAux ax;
-        ax.min_x = s_red[0];
-        ax.min_y = s_red[2];
-        uint32_t rx = (uint32_t)(s_red[1] - s_red[0]);
-        uint32_t ry = (uint32_t)(s_red[3] - s_red[2]);
-        uint32_t nb = ceil_log2((uint32_t)(m > 1 ? m : 2));
-        // 32-bit keys need (range << nb) + j < 2^32
-        bool fits = m > 0 && nb < 32 && ((rx | ry) >> (32 - nb)) == 0u;
-        ax.nb = fits ? nb : 0u;
-        ax.flags = s_red[4] ? kFlagOffGrid : 0u;
-        a.aux[w] = ax;
-    }
+    int32_t *scratch = reinterpret_cast<int32_t *>(buf);
+    sort_marginal(d.x, m, scratch, out);
+    sort_marginal(d.y, m, scratch, out + m);
+    __threadfence();  // release: this wave's stores reach every XCD before the flag
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicExch(&a.ready[w], 1u);
 }
 
 // --------------------------------------------------------------------------
@@ -365,6 +324,78 @@ __device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, i
 // split items: one block of up to 512 query points of a large window
 // --------------------------------------------------------------------------
 
+// Window extrema and grid check, computed by the workgroup (every item of a
+// window computes the same values).
+__device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
+{
+    const int tid = threadIdx.x;
+    const int m = (int)d.m;
+    if (tid == 0) {
+        s_red[0] = INT32_MAX;
+        s_red[1] = INT32_MIN;
+        s_red[2] = INT32_MAX;
+        s_red[3] = INT32_MIN;
+        s_red[4] = 0;
+    }
+    __syncthreads();
+    int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
+    uint32_t off = 0;
+    for (int i = tid; i < m; i += kBlock) {
+        const int32_t xi = grid_int(d.x[i], off), yi = grid_int(d.y[i], off);
+        mnx = min(mnx, xi);
+        mxx = max(mxx, xi);
+        mny = min(mny, yi);
+        mxy = max(mxy, yi);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = min(mnx, __shfl_xor(mnx, o, 64));
+        mxx = max(mxx, __shfl_xor(mxx, o, 64));
+        mny = min(mny, __shfl_xor(mny, o, 64));
+        mxy = max(mxy, __shfl_xor(mxy, o, 64));
+        off |= (uint32_t)__shfl_xor((int)off, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        atomicMin(&s_red[0], mnx);
+        atomicMax(&s_red[1], mxx);
+        atomicMin(&s_red[2], mny);
+        atomicMax(&s_red[3], mxy);
+        if (off)
+            atomicOr(&s_red[4], 1);
+    }
+    __syncthreads();
+    WinAux ax;
+    ax.min_x = s_red[0];
+    ax.min_y = s_red[2];
+    const uint32_t rx = (uint32_t)(s_red[1] - s_red[0]);
+    const uint32_t ry = (uint32_t)(s_red[3] - s_red[2]);
+    const uint32_t nb = ceil_log2((uint32_t)(m > 1 ? m : 2));
+    // 32-bit keys need (range << nb) + j < 2^32
+    ax.nb = (((rx | ry) >> (32 - nb)) == 0u) ? nb : 0u;
+    ax.flags = s_red[4] ? kFlagOffGrid : 0u;
+    __syncthreads();
+    return ax;
+}
+
+// Wait until window w's sorted marginals are in HBM.  The prep item has a
+// lower index than every split item, so a running workgroup already holds it
+// and it waits on nothing: the wait ends.  A poll limit turns a broken
+// dependency into an error report instead of a hang.
+__device__ void wait_ready(const LaunchArgs &a, uint32_t w)
+{
+    if (threadIdx.x == 0) {
+        uint32_t polls = 0;
+        while (atomicAdd(&a.ready[w], 0u) == 0u) {
+            if (++polls >= kWaitLimit) {
+                atomicOr(a.err, kErrWait);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    __syncthreads();
+    __threadfence();  // acquire: later loads see the prep item's stores
+}
+
 constexpr int kChunk = 2048;  // candidates (and sorted-marginal entries) staged in LDS at a time
 
 // (X - min) << nb for point i of a window: a 32-bit key coordinate (nb > 0)
@@ -483,8 +514,8 @@ __device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int s
 }
 
 template <int K, int Q>
-__device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDesc &d, const WinAux &ax, int q0,
-                                                uint32_t *buf)
+__device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w, const WinDesc &d, const WinAux &ax,
+                                                int q0, uint32_t *buf)
 {
     constexpr int S = K + 1;
     const int m = (int)d.m;
@@ -556,6 +587,7 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDe
                                                0xFFFu, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
     }
     // ---- marginal counts over the sorted marginals, chunk by chunk
+    wait_ready(a, w);
     int32_t xi[Q], yi[Q];
     int hx[Q], lx[Q], hy[Q], ly[Q];
 #pragma unroll
@@ -621,18 +653,19 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, const WinDe
 }
 
 template <int K>
-__device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *buf, long long *s_part)
+__device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *buf, long long *s_part,
+                           int32_t *s_red)
 {
     const WinDesc d = a.win[w];
-    const WinAux ax = a.aux[w];
+    const WinAux ax = window_aux(d, s_red);
     const int m = (int)d.m;
     const int tid = threadIdx.x;
     long long part = 0;
     if (m > K) {
         if (m - q0 <= kBlock)
-            part = split_body<K, 1>(a, d, ax, q0, buf);
+            part = split_body<K, 1>(a, w, d, ax, q0, buf);
         else
-            part = split_body<K, 2>(a, d, ax, q0, buf);
+            part = split_body<K, 2>(a, w, d, ax, q0, buf);
     }
     // workgroup sum of the fixed-point terms (exact, order-free)
     for (int o = 32; o > 0; o >>= 1)
@@ -962,6 +995,7 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
     __shared__ long long s_part[kBlock / 64];
+    __shared__ int32_t s_red[5];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
 
@@ -984,12 +1018,14 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
         const Item itm = a.item[a.item_begin + it];
         if (itm.info & kItemLocal) {
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
+        } else if (itm.info & kItemPrep) {
+            prep_item(a, itm.win, buf);
         } else {
             // split items are the largest, taken first: let their waves issue
             // ahead of the short local items sharing the CU, so they are not
             // the last to finish
             __builtin_amdgcn_s_setprio(2);
-            split_item<K>(a, itm.win, (int)itm.info, buf, s_part);
+            split_item<K>(a, itm.win, (int)itm.info, buf, s_part, s_red);
             __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
@@ -999,6 +1035,15 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
             s_item = atomicAdd(a.counter, 1u);
         __syncthreads();
     }
+}
+
+// plain form: one workgroup per split window, before that window's items
+__global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
+{
+    __shared__ __align__(16) uint32_t buf[kMaxWindow];
+    const uint32_t pi = a.win_begin + blockIdx.x;
+    if (pi < a.n_prep)
+        prep_item(a, a.prep_list[pi], buf);
 }
 
 // --------------------------------------------------------------------------

@@ -135,4 +135,29 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         out.first_item.push_back((uint32_t)out.items.size());
 }
 
+// Batched form: the queue the persistent kernel takes items from.  Prep
+// items (one per split window, largest first) come first; then the other
+// items, largest cost first (a stable bucket order by log2(cost) is enough
+// for the greedy schedule).  Split items wait for their window's prep item
+// only before their counting phase.
+inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vector<Item> &queue)
+{
+    queue.clear();
+    queue.reserve(P.items.size() + P.prep_list.size());
+    std::vector<uint32_t> prep(P.prep_list);
+    std::stable_sort(prep.begin(), prep.end(), [&](uint32_t a, uint32_t b) { return wm[a] > wm[b]; });
+    for (uint32_t w : prep)
+        queue.push_back(Item{w, kItemPrep});
+    std::vector<uint32_t> cnt(66, 0);
+    auto bucket = [](uint64_t c) { return 63 - (63 - __builtin_clzll(c | 1ull)); };
+    for (uint64_t c : P.cost)
+        cnt[bucket(c) + 1]++;
+    for (int i = 1; i <= 65; ++i)
+        cnt[i] += cnt[i - 1];
+    const size_t base = queue.size();
+    queue.resize(base + P.items.size());
+    for (size_t i = 0; i < P.items.size(); ++i)
+        queue[base + cnt[bucket(P.cost[i])]++] = P.items[i];
+}
+
 }  // namespace wmi

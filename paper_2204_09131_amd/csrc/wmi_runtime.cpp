@@ -231,15 +231,15 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
             HIPCHK(st, hipEventRecord(ev->m1, s));
         }
     } else {
-        HIPCHK(st, launch_prep(a, a.n_prep, s));
+        // prep items run inside the main kernel, at the head of its queue
         if (ev)
             HIPCHK(st, hipEventRecord(ev->m0, s));
         HIPCHK(st, launch_main(a, b->grid, s));
         if (ev)
             HIPCHK(st, hipEventRecord(ev->m1, s));
     }
-    if (b->count)
-        HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->count * sizeof(Result), hipMemcpyDeviceToHost, s));
+    HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->count * sizeof(Result) + sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
     return WMI_OK;
 }
 
@@ -343,6 +343,10 @@ int finish_if_done(wmi_batch *b, bool block, int64_t timeout_us)
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ev.s0, ev.s1) == hipSuccess)
             b->stats.device_ms = ms;
+        uint32_t err = 0;
+        std::memcpy(&err, reinterpret_cast<const char *>(b->h_res) + b->count * sizeof(Result), sizeof err);
+        if (err)
+            return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
     }
     return WMI_OK;
 }
@@ -675,7 +679,10 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
                           &first_item = plan.first_item;
     std::vector<int32_t> &wprep = plan.wprep;
     const uint64_t split_pts = plan.split_pts;
-    const uint64_t n_items = items.size();
+    std::vector<Item> queue;
+    if (!plain)
+        plan_queue(plan, wm, queue);
+    const uint64_t n_items = plain ? items.size() : queue.size();
     const uint64_t n_prep = prep_list.size();
     if (split_pts > 0xFFFFFFF0ull)
         return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu points in large windows)",
@@ -696,8 +703,11 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     size_t o_counter = align_up(o_qdone + count * sizeof(uint32_t), A);
     size_t o_wmi = align_up(o_counter + sizeof(uint32_t), A);
     size_t o_wflags = align_up(o_wmi + n_win * sizeof(double), A);
-    size_t o_res = align_up(o_wflags + n_win * sizeof(uint32_t), A);
-    size_t dev_bytes = align_up(o_res + count * sizeof(Result), A);
+    size_t o_ready = align_up(o_wflags + n_win * sizeof(uint32_t), A);
+    size_t o_res = align_up(o_ready + n_win * sizeof(uint32_t), A);
+    // results and the error word are downloaded together
+    size_t res_bytes = count * sizeof(Result) + sizeof(uint32_t);
+    size_t dev_bytes = align_up(o_res + res_bytes, A);
 
     if (dev_bytes > st->budget)
         return fail(WMI_ENOMEM, "wmi_submit: batch needs %zu bytes of device memory, budget is %llu", dev_bytes,
@@ -745,7 +755,7 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     hipError_t e = hipMalloc(&b->dev, dev_bytes);
     if (e != hipSuccess)
         return bail(e, "hipMalloc(batch)");
-    b->host_bytes = desc_bytes + align_up(count * sizeof(Result), A);
+    b->host_bytes = desc_bytes + align_up(res_bytes, A);
     e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, A), hipHostMallocDefault);
     if (e != hipSuccess)
         return bail(e, "hipHostMalloc(batch)");
@@ -785,17 +795,9 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         b->win_prep = std::move(wprep);
         std::copy(items.begin(), items.end(), hi);
     } else {
-        // largest first; a stable bucket order by log2(cost) is enough for
-        // the greedy schedule of the persistent kernel
-        std::vector<uint32_t> cnt(66, 0);
-        auto bucket = [&](uint64_t c) { return 63 - (63 - __builtin_clzll(c | 1ull)); };
-        for (uint64_t i = 0; i < n_items; ++i)
-            cnt[bucket(cost[i]) + 1]++;
-        for (int i = 1; i <= 65; ++i)
-            cnt[i] += cnt[i - 1];
-        for (uint64_t i = 0; i < n_items; ++i)
-            hi[cnt[bucket(cost[i])]++] = items[i];
+        std::copy(queue.begin(), queue.end(), hi);
     }
+    (void)cost;
 
     // ---- launch arguments -----------------------------------------------------
     LaunchArgs &a = b->args;
@@ -811,6 +813,8 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     a.wmi = reinterpret_cast<double *>(b->dev + o_wmi);
     a.wflags = reinterpret_cast<uint32_t *>(b->dev + o_wflags);
     a.res = reinterpret_cast<Result *>(b->dev + o_res);
+    a.err = reinterpret_cast<uint32_t *>(b->dev + o_res + count * sizeof(Result));
+    a.ready = reinterpret_cast<uint32_t *>(b->dev + o_ready);
     a.psi_d = st->psi_d;
     a.psi_fix = st->psi_fix;
     a.prep_list = reinterpret_cast<const uint32_t *>(b->dev + o_prep);

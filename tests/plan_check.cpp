@@ -1,6 +1,7 @@
 // Host-side check of the batch work list (csrc/wmi_plan.h) on random query
 // mixes: every window covered exactly once, and every item within the limits
 // the main kernel's LDS layout assumes.  Prints OK or the first violation.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -85,6 +86,40 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
     if (pi != P.prep_list.size() || pts != P.split_pts)
         return fail("prep totals", (long)pi, (long)pts);
     if (!plain) {
+        // the queue: every item once, one prep item per split window, and
+        // every prep item ahead of every split item (the split items' wait
+        // for their window's sorted marginals relies on this order)
+        std::vector<Item> queue;
+        plan_queue(P, wm, queue);
+        if (queue.size() != P.items.size() + P.prep_list.size())
+            return fail("queue size", (long)queue.size(), (long)P.items.size());
+        size_t first_other = queue.size(), last_prep = 0, nprep = 0;
+        std::vector<int> prep_seen(n, 0);
+        for (size_t i = 0; i < queue.size(); ++i) {
+            if (queue[i].info == kItemPrep) {
+                if (queue[i].win >= n || wm[queue[i].win] <= (uint32_t)kLocalSlots)
+                    return fail("prep item of a small window", (long)i, (long)queue[i].win);
+                prep_seen[queue[i].win]++;
+                last_prep = i;
+                ++nprep;
+            } else if (first_other == queue.size()) {
+                first_other = i;
+            }
+        }
+        if (nprep && last_prep > first_other)
+            return fail("prep item after another item", (long)last_prep, (long)first_other);
+        for (size_t w = 0; w < n; ++w)
+            if ((wm[w] > (uint32_t)kLocalSlots) != (prep_seen[w] == 1))
+                return fail("prep items per window", (long)w, (long)prep_seen[w]);
+        std::vector<uint64_t> a, b;
+        for (const Item &I : P.items)
+            a.push_back(((uint64_t)I.win << 32) | I.info);
+        for (size_t i = nprep; i < queue.size(); ++i)
+            b.push_back(((uint64_t)queue[i].win << 32) | queue[i].info);
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a != b)
+            return fail("queue is not a permutation of the items", (long)a.size(), (long)b.size());
         // a query whose windows are all local and fit one item is not cut
         size_t w = 0;
         for (uint64_t t = 0; t < count; ++t) {
