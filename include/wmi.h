@@ -232,6 +232,98 @@ int wmi_batch_destroy(wmi_batch *batch);
 int wmi_debug_window(wmi_store *store, const wmi_query *query, const wmi_params *params,
                      uint32_t *host_nx, uint32_t *host_ny, float *host_eps_x, float *host_eps_y);
 
+/* ==========================================================================
+ * Serving: continuous batching of range requests over resident series.
+ *
+ * A request asks for the MI of every window of w points starting at start,
+ * start + stride, ... that lies inside [start, end) of the pair (a, b) -- the
+ * sliding-window sweep a correlation search submits (Sections 5.1 and 5.2).
+ * A scheduler thread admits requests in arrival order while their results
+ * fit the server's HBM arena (the admission budget), then keeps building
+ * launches from the windows of every admitted request not yet scheduled:
+ * requests arriving while others run join the next launch, long requests are
+ * cut across launches, and two launch slots keep the device busy while the
+ * next launch is prepared.  A request completes when all its windows are
+ * done and its results are back in host memory.  Results are exact and do not
+ * depend on how requests were batched.
+ * ========================================================================== */
+
+typedef struct wmi_server wmi_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;   /* result arena for admitted requests; 0 = 256 MiB */
+    uint32_t k;                  /* estimator parameters of every request        */
+    uint32_t estimator;
+    uint32_t max_launch_windows; /* windows per launch; 0 = 65536                 */
+    uint32_t flags;              /* 0                                             */
+} wmi_server_desc;
+
+typedef struct {                 /* 32 bytes */
+    uint32_t a, b;               /* series pair (x from a, y from b)              */
+    uint64_t start;              /* first window start                            */
+    uint64_t end;                /* windows lie in [start, end); end <= lengths   */
+    uint32_t w;                  /* window points, 1..WMI_MAX_WINDOW              */
+    uint32_t stride;             /* >= 1                                           */
+} wmi_request;
+
+typedef struct {                 /* 16 bytes */
+    double mi;                   /* nats; NaN with WMI_F_TOO_SHORT when w <= k    */
+    uint32_t flags;              /* WMI_F_TOO_SHORT, WMI_F_OFFGRID                 */
+    uint32_t reserved;
+} wmi_window_result;
+
+typedef struct {
+    uint64_t windows;            /* windows of the request                       */
+    double t_arrival_us;         /* server clock (microseconds) at submit        */
+    double t_admit_us;           /* admitted into the arena                      */
+    double t_first_launch_us;    /* its first windows launched                   */
+    double t_complete_us;        /* results in host memory                       */
+    int32_t state;               /* 0 queued, 1 admitted, 2 done, < 0 WMI_E code */
+    uint32_t launches;           /* launches its windows were spread over         */
+} wmi_request_info;
+
+typedef struct {
+    uint64_t requests_done;
+    uint64_t windows_done;
+    uint64_t ordered_pairs_done;
+    uint64_t launches;
+    double busy_us;              /* sum of launch durations (events)            */
+    uint64_t arena_bytes;        /* admission budget                             */
+    uint64_t arena_peak_bytes;   /* most arena bytes held at once                */
+    uint64_t queued_peak;        /* most requests waiting for admission at once   */
+} wmi_server_stats;
+
+/* Start a server on a store (its series stay owned by the store; a series
+ * read by a pending request cannot be removed).  Allocates the arena and two
+ * launch slots and starts the scheduler thread. */
+int wmi_server_create(wmi_store *store, const wmi_server_desc *desc, wmi_server **out);
+
+/* Enqueue a request (copied); never blocks.  *ticket identifies it.
+ * WMI_EINVAL for a bad series id, window or stride; WMI_ENOMEM if its results
+ * alone exceed the arena. */
+int wmi_server_submit(wmi_server *server, const wmi_request *request, uint64_t *ticket);
+
+/* Wait up to timeout_us (< 0: forever) for a request to complete. */
+int wmi_server_wait(wmi_server *server, uint64_t ticket, int64_t timeout_us);
+
+/* Progress and timestamps of a request (any state). */
+int wmi_server_info(wmi_server *server, uint64_t ticket, wmi_request_info *info);
+
+/* Copy a completed request's results (info->windows entries, in window
+ * order) to host_out, which holds `capacity` entries, then forget the ticket.
+ * WMI_ESTATE if not complete; WMI_EINVAL if capacity is too small. */
+int wmi_server_read(wmi_server *server, uint64_t ticket, wmi_window_result *host_out, uint64_t capacity,
+                    wmi_request_info *info);
+
+/* Server counters. */
+int wmi_server_stats_get(wmi_server *server, wmi_server_stats *out);
+
+/* Current server clock in microseconds (the clock of wmi_request_info). */
+double wmi_server_clock_us(wmi_server *server);
+
+/* Finish every pending request, stop the scheduler and free the server. */
+int wmi_server_destroy(wmi_server *server);
+
 /* Copy the library's double-precision digamma table psi(1..n) (n <= 8192)
  * to host_out (for checks against an independent construction). */
 int wmi_psi_table(uint32_t n, double *host_out);

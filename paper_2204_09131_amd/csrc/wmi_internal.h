@@ -72,6 +72,31 @@ struct Result {             // 32 bytes, same layout as wmi_result
     uint32_t flags, reserved;
 };
 
+// Serving: results of single windows, 16 bytes, written into request slices
+// of an HBM arena.
+struct CompactResult {
+    double mi;
+    uint32_t flags, reserved;
+};
+
+// Serving: a run of windows of one request inside a launch: `count` windows
+// of m points starting at start, start + stride, ... on series (x, y).  The
+// expand kernel turns parts into window descriptors and queue items.
+struct PartDesc {           // 64 bytes
+    const float *x;         // series a (window 0 starts at x + start)
+    const float *y;         // series b
+    uint64_t start;
+    uint64_t dst;           // arena index of the part's first window result
+    uint32_t stride;
+    uint32_t count;
+    uint32_t m;
+    uint32_t win0;          // launch index of the part's first window
+    uint32_t sorted0;       // sorted-marginal offset of its first window (m > kLocalSlots)
+    uint32_t prep0;         // queue index of its first prep item (m > kLocalSlots)
+    uint32_t item0;         // queue index of its first split / local item
+    uint32_t per_item;      // local windows per item (m <= kLocalSlots)
+};
+
 struct LaunchArgs {
     const WinDesc *win;
     const Item *item;
@@ -99,6 +124,9 @@ struct LaunchArgs {
     uint32_t n_prep;
     uint32_t *ready;              // per window: its sorted marginals are in HBM
     uint32_t *err;                // error word (kErrWait)
+    // serving: per-query arena index of the result, or null (results in res)
+    const uint64_t *cdst;
+    CompactResult *arena;
     // debug export (one window): per point counts and radii, or null
     uint32_t *dbg_nx, *dbg_ny;
     float *dbg_ex, *dbg_ey;

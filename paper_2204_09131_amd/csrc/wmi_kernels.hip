@@ -234,6 +234,21 @@ __device__ __forceinline__ Result compose_result(const QDesc &qd, const double *
     return r;
 }
 
+// Store a query's result: the 32-byte result array, or for serving the
+// 16-byte slot of its request in the arena.
+__device__ __forceinline__ void store_result(const LaunchArgs &a, uint32_t q, const Result &r)
+{
+    if (a.cdst) {
+        CompactResult c;
+        c.mi = r.mi_base;
+        c.flags = r.flags;
+        c.reserved = 0u;
+        a.arena[a.cdst[q]] = c;
+    } else {
+        a.res[q] = r;
+    }
+}
+
 // A window's final estimate, reported to its query by one thread.  A plain
 // query is written directly; a triple whose windows finished in different
 // workgroups is completed by whichever finishes last.
@@ -241,7 +256,7 @@ __device__ void report_window(const LaunchArgs &a, uint32_t w, uint32_t q, doubl
 {
     const QDesc qd = a.qd[q];
     if (qd.nwin == 1) {
-        a.res[q] = compose_result(qd, &mi, &fl);
+        store_result(a, q, compose_result(qd, &mi, &fl));
         return;
     }
     publish_f64(&a.wmi[w], mi);
@@ -255,7 +270,7 @@ __device__ void report_window(const LaunchArgs &a, uint32_t w, uint32_t q, doubl
             m3[r] = fetch_f64(&a.wmi[qd.win0 + r]);
             f3[r] = atomicAdd(&a.wflags[qd.win0 + r], 0u);
         }
-        a.res[q] = compose_result(qd, m3, f3);
+        store_result(a, q, compose_result(qd, m3, f3));
     }
 }
 
@@ -979,7 +994,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         const bool inside = qd.win0 >= w0 && qd.win0 + qd.nwin <= w0 + nwin;
         if (inside) {
             if (qd.win0 == w)
-                a.res[q] = compose_result(qd, &L.mi[tid], &L.flags[tid]);
+                store_result(a, q, compose_result(qd, &L.mi[tid], &L.flags[tid]));
         } else {
             report_window(a, w, q, L.mi[tid], L.flags[tid]);
         }
@@ -1037,6 +1052,49 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
     }
 }
 
+// --------------------------------------------------------------------------
+// serving: expand range parts into windows, queries and queue items
+// --------------------------------------------------------------------------
+// One workgroup per part.  Window w of the part: descriptor, a one-window
+// query writing to arena index dst + w.  Split windows (m > kLocalSlots): a
+// prep item each, then ceil(m / kSplitPoints) split items each.  Local
+// windows: items of per_item consecutive windows.
+__global__ __launch_bounds__(kBlock) void expand_kernel(LaunchArgs a, const PartDesc *parts, uint32_t n_parts,
+                                                        Item *queue, WinDesc *win, QDesc *qd, uint64_t *cdst)
+{
+    const uint32_t pi = blockIdx.x;
+    if (pi >= n_parts)
+        return;
+    const PartDesc P = parts[pi];
+    const bool split = P.m > (uint32_t)kLocalSlots;
+    const uint32_t nsplit = (P.m + kSplitPoints - 1) / kSplitPoints;
+    for (uint32_t i = threadIdx.x; i < P.count; i += kBlock) {
+        const uint32_t w = P.win0 + i;
+        WinDesc d;
+        d.x = P.x + P.start + (uint64_t)i * P.stride;
+        d.y = P.y + P.start + (uint64_t)i * P.stride;
+        d.m = P.m;
+        d.query = w;
+        d.sorted_off = split ? P.sorted0 + i * P.m : 0u;
+        d.n_items = split ? nsplit : 1u;
+        win[w] = d;
+        QDesc q;
+        q.win0 = w;
+        q.nwin = 1u;
+        q.tau_eff = 0.0;
+        qd[w] = q;
+        cdst[w] = P.dst + i;
+        if (split) {
+            queue[P.prep0 + i] = Item{w, kItemPrep};
+            for (uint32_t t = 0; t < nsplit; ++t)
+                queue[P.item0 + i * nsplit + t] = Item{w, t * (uint32_t)kSplitPoints};
+        } else if (i % P.per_item == 0) {
+            const uint32_t n = min(P.per_item, P.count - i);
+            queue[P.item0 + i / P.per_item] = Item{w, kItemLocal | n};
+        }
+    }
+}
+
 // plain form: one workgroup per split window, before that window's items
 __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
 {
@@ -1079,6 +1137,15 @@ __global__ void validate_kernel(const float *v, uint64_t n, unsigned long long *
 // --------------------------------------------------------------------------
 // host-side launchers
 // --------------------------------------------------------------------------
+
+hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_parts, Item *queue, WinDesc *win,
+                         QDesc *qd, uint64_t *cdst, hipStream_t s)
+{
+    if (n_parts == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(expand_kernel, dim3(n_parts), dim3(kBlock), 0, s, a, parts, n_parts, queue, win, qd, cdst);
+    return hipGetLastError();
+}
 
 hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s)
 {

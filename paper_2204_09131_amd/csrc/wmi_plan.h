@@ -160,4 +160,54 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
         queue[base + cnt[bucket(P.cost[i])]++] = P.items[i];
 }
 
+// Serving: local windows per item for a run of windows of m points (the
+// local-item limits above, every window of the run the same size).
+inline uint32_t plan_local_per_item(uint32_t m)
+{
+    const uint32_t even = (m + 1u) & ~1u;
+    const uint32_t n = std::min<uint32_t>((uint32_t)kLocalWindows, (uint32_t)kLocalSlots / even);
+    return std::max(1u, std::min(n, (uint32_t)kLocalSort / plan_pow2(std::max(m, 2u))));
+}
+
+// Serving: queue layout of a launch made of parts (m and count set, in launch
+// window order).  Sets win0, and per part its prep items, sorted-marginal
+// offset and items: all prep items first, then split items, then local
+// items, larger windows first within each.  Returns the queue length; *split
+// receives the sorted-marginal points (sum of m over split windows).
+inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split)
+{
+    std::vector<uint32_t> order(n);
+    uint32_t win0 = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        order[i] = i;
+        pd[i].win0 = win0;
+        win0 += pd[i].count;
+        pd[i].prep0 = pd[i].sorted0 = pd[i].item0 = 0;
+        pd[i].per_item = 1;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return pd[a].m > pd[b].m; });
+    uint32_t q = 0;
+    uint64_t sorted = 0;
+    for (uint32_t i : order)
+        if (pd[i].m > (uint32_t)kLocalSlots) {
+            pd[i].prep0 = q;
+            pd[i].sorted0 = (uint32_t)sorted;
+            q += pd[i].count;
+            sorted += (uint64_t)pd[i].count * pd[i].m;
+        }
+    for (uint32_t i : order)
+        if (pd[i].m > (uint32_t)kLocalSlots) {
+            pd[i].item0 = q;
+            q += pd[i].count * ((pd[i].m + kSplitPoints - 1) / kSplitPoints);
+        }
+    for (uint32_t i : order)
+        if (pd[i].m <= (uint32_t)kLocalSlots) {
+            pd[i].item0 = q;
+            pd[i].per_item = plan_local_per_item(pd[i].m);
+            q += (pd[i].count + pd[i].per_item - 1) / pd[i].per_item;
+        }
+    *split = sorted;
+    return q;
+}
+
 }  // namespace wmi

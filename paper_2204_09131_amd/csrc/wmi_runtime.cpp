@@ -28,15 +28,8 @@
 #include "wmi.h"
 #include "wmi_internal.h"
 #include "wmi_plan.h"
+#include "wmi_store.h"
 
-namespace wmi {
-hipError_t launch_clear(const LaunchArgs &a, hipStream_t s);
-hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s);
-hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s);
-hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s);
-int main_occupancy(uint32_t k);
-void build_psi_tables(int n_max, std::vector<double> &psi_d, std::vector<long long> &psi_fix);
-}  // namespace wmi
 
 using namespace wmi;
 
@@ -44,9 +37,7 @@ static_assert(sizeof(wmi_query) == 32, "wmi_query layout");
 static_assert(sizeof(wmi_result) == 32 && sizeof(Result) == 32, "result layout");
 static_assert(sizeof(WinDesc) == 32 && sizeof(Item) == 8 && sizeof(QDesc) == 16, "descriptors");
 
-namespace {
-
-constexpr uint64_t kDefaultBudget = 1ull << 30;
+namespace wmi {
 
 thread_local std::string g_err;
 
@@ -61,52 +52,25 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0)
-            (void)hipSetDevice(prev);
-    }
-};
+const char *last_error() { return g_err.c_str(); }
 
-struct Series {
-    const float *d = nullptr;
-    uint64_t n = 0;
-    bool owned = false;
-    bool live = false;
-    bool offgrid = false;
-    uint32_t busy = 0;
-};
+int poison(wmi_store *st, hipError_t e, const char *what)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    st->poisoned = true;
+    st->poison_msg = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(WMI_EHIP, "%s", st->poison_msg.c_str());
+}
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int check_poison(wmi_store *st)
+{
+    std::lock_guard<std::mutex> lk(st->mu);
+    if (st->poisoned)
+        return fail(WMI_EHIP, "store poisoned by an earlier HIP error: %s", st->poison_msg.c_str());
+    return WMI_OK;
+}
 
-}  // namespace
-
-struct wmi_store {
-    int device = 0;
-    uint32_t flags = 0;
-    uint64_t budget = kDefaultBudget;
-    hipStream_t stream = nullptr;
-    hipStream_t capture_stream = nullptr;
-    double *psi_d = nullptr;
-    long long *psi_fix = nullptr;
-    int cu_count = 1;
-    std::mutex mu;
-    std::condition_variable cv;
-    std::vector<Series> series;
-    uint64_t inflight = 0;
-    bool poisoned = false;
-    std::string poison_msg;
-    std::set<wmi_batch *> batches;
-};
+}  // namespace wmi
 
 // Events of one run: start, prep start, main start, main end, end.
 struct RunEvents {
@@ -148,29 +112,6 @@ struct wmi_batch {
 };
 
 namespace {
-
-int poison(wmi_store *st, hipError_t e, const char *what)
-{
-    std::lock_guard<std::mutex> lk(st->mu);
-    st->poisoned = true;
-    st->poison_msg = std::string(what) + ": " + hipGetErrorString(e);
-    return fail(WMI_EHIP, "%s", st->poison_msg.c_str());
-}
-
-#define HIPCHK(st, expr)                          \
-    do {                                          \
-        hipError_t e_ = (expr);                   \
-        if (e_ != hipSuccess)                     \
-            return poison((st), e_, #expr);       \
-    } while (0)
-
-int check_poison(wmi_store *st)
-{
-    std::lock_guard<std::mutex> lk(st->mu);
-    if (st->poisoned)
-        return fail(WMI_EHIP, "store poisoned by an earlier HIP error: %s", st->poison_msg.c_str());
-    return WMI_OK;
-}
 
 bool value_on_grid(float v)
 {
@@ -439,6 +380,13 @@ int wmi_store_destroy(wmi_store *st)
     }
     for (wmi_batch *b : bs)
         wmi_batch_destroy(b);
+    std::vector<wmi_server *> ss;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        ss.assign(st->servers.begin(), st->servers.end());
+    }
+    for (wmi_server *sv : ss)
+        wmi_server_destroy(sv);
     (void)hipStreamSynchronize(st->stream);
     for (Series &s : st->series)
         if (s.live && s.owned)

@@ -41,12 +41,17 @@ QUERY_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("len", "<
                         ("ext_len", "<u4"), ("ext_side", "<i4"), ("pad", "<u4")])
 RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f8"),
                          ("flags", "<u4"), ("pad", "<u4")])
+REQUEST_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("end", "<u8"), ("w", "<u4"),
+                          ("stride", "<u4")])
+WINDOW_RESULT_DTYPE = np.dtype([("mi", "<f8"), ("flags", "<u4"), ("pad", "<u4")])
 
 # the symbols include/wmi.h declares
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
            "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
-           "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table")
+           "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
+           "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
+           "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy")
 REPLAY_DIRECT = 1
 
 
@@ -75,6 +80,24 @@ class _Stats(ctypes.Structure):
                 ("launches", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("items", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
                 ("cus", ctypes.c_uint32)]
+
+
+class _ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("k", ctypes.c_uint32), ("estimator", ctypes.c_uint32),
+                ("max_launch_windows", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("windows", ctypes.c_uint64), ("t_arrival_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_first_launch_us", ctypes.c_double), ("t_complete_us", ctypes.c_double),
+                ("state", ctypes.c_int32), ("launches", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_uint64), ("windows_done", ctypes.c_uint64),
+                ("ordered_pairs_done", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("busy_us", ctypes.c_double), ("arena_bytes", ctypes.c_uint64),
+                ("arena_peak_bytes", ctypes.c_uint64), ("queued_peak", ctypes.c_uint64)]
 
 
 _lib = None
@@ -110,6 +133,14 @@ def lib():
         "wmi_batch_destroy": ([vp], ctypes.c_int),
         "wmi_debug_window": ([vp, vp, P(_Params), vp, vp, vp, vp], ctypes.c_int),
         "wmi_psi_table": ([u32, vp], ctypes.c_int),
+        "wmi_server_create": ([vp, P(_ServerDesc), P(vp)], ctypes.c_int),
+        "wmi_server_submit": ([vp, vp, P(u64)], ctypes.c_int),
+        "wmi_server_wait": ([vp, u64, i64], ctypes.c_int),
+        "wmi_server_info": ([vp, u64, P(_RequestInfo)], ctypes.c_int),
+        "wmi_server_read": ([vp, u64, vp, u64, P(_RequestInfo)], ctypes.c_int),
+        "wmi_server_stats_get": ([vp, P(_ServerStats)], ctypes.c_int),
+        "wmi_server_clock_us": ([vp], ctypes.c_double),
+        "wmi_server_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -287,3 +318,72 @@ class Store:
         _check(lib().wmi_debug_window(self.h, q.ctypes.data, ctypes.byref(p), nx.ctypes.data,
                                       ny.ctypes.data, ex.ctypes.data, ey.ctypes.data))
         return {"nx": nx, "ny": ny, "eps_x": ex, "eps_y": ey}
+
+
+def _info_dict(i: _RequestInfo) -> dict:
+    return {"windows": i.windows, "t_arrival_us": i.t_arrival_us, "t_admit_us": i.t_admit_us,
+            "t_first_launch_us": i.t_first_launch_us, "t_complete_us": i.t_complete_us,
+            "state": i.state, "launches": i.launches}
+
+
+class Server:
+    """Continuous batching of range requests over a store's series."""
+
+    def __init__(self, store: Store, k: int = 4, estimator: int = 0, hbm_budget_bytes: int = 0,
+                 max_launch_windows: int = 0):
+        d = _ServerDesc(int(hbm_budget_bytes), int(k), int(estimator), int(max_launch_windows), 0)
+        h = ctypes.c_void_p()
+        _check(lib().wmi_server_create(store.h, ctypes.byref(d), ctypes.byref(h)))
+        self.store = store
+        self.h = h
+        self._windows = {}
+
+    def submit(self, a: int, b: int, start: int, end: int, w: int, stride: int = 1) -> int:
+        r = np.zeros(1, dtype=REQUEST_DTYPE)
+        r["a"], r["b"], r["start"], r["end"], r["w"], r["stride"] = a, b, start, end, w, stride
+        t = ctypes.c_uint64()
+        _check(lib().wmi_server_submit(self.h, r.ctypes.data, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        _check(lib().wmi_server_wait(self.h, int(ticket), int(timeout_us)))
+
+    def info(self, ticket: int) -> dict:
+        i = _RequestInfo()
+        _check(lib().wmi_server_info(self.h, int(ticket), ctypes.byref(i)))
+        return _info_dict(i)
+
+    def read(self, ticket: int):
+        """Results (WINDOW_RESULT_DTYPE, window order) and timing of a completed request."""
+        n = self.info(ticket)["windows"]
+        out = np.zeros(n, dtype=WINDOW_RESULT_DTYPE)
+        i = _RequestInfo()
+        _check(lib().wmi_server_read(self.h, int(ticket), out.ctypes.data if n else None, n, ctypes.byref(i)))
+        return out, _info_dict(i)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().wmi_server_stats_get(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def clock_us(self) -> float:
+        return lib().wmi_server_clock_us(self.h)
+
+    def close(self):
+        # a closed store has already destroyed its servers
+        if self.h and self.store.h:
+            _check(lib().wmi_server_destroy(self.h))
+        self.h = ctypes.c_void_p(None)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self.h and self.store.h:
+                lib().wmi_server_destroy(self.h)
+        except Exception:
+            pass

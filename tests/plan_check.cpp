@@ -1,6 +1,7 @@
-// Host-side check of the batch work list (csrc/wmi_plan.h) on random query
-// mixes: every window covered exactly once, and every item within the limits
-// the main kernel's LDS layout assumes.  Prints OK or the first violation.
+// Host-side check of the work lists (csrc/wmi_plan.h): the batch plan on
+// random query mixes (every window covered exactly once, every item within
+// the limits the main kernel's LDS layout assumes) and the queue layout of
+// serving launches.  Prints OK or the first violation.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -151,6 +152,81 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
     return 0;
 }
 
+// Serving launches: expand the parts as the expand kernel does (one window
+// descriptor per window, prep / split / local items at the offsets the plan
+// gives) and check every queue entry is written once, every window covered,
+// sorted-marginal ranges disjoint and inside the total, and local items
+// within the kernel's limits.
+static int check_parts(std::vector<PartDesc> pd)
+{
+    uint64_t split = 0;
+    const uint32_t n_items = plan_parts(pd.data(), (uint32_t)pd.size(), &split);
+    uint64_t n_win = 0;
+    for (const PartDesc &p : pd) {
+        if (p.win0 != n_win)
+            return fail("part win0", (long)p.win0, (long)n_win);
+        n_win += p.count;
+    }
+    std::vector<int> queue(n_items, 0);  // 1 prep, 2 split, 3 local
+    std::vector<int> covered(n_win, 0), prepped(n_win, 0);
+    std::vector<char> sorted_used(split, 0);
+    uint32_t last_prep = 0, first_split = n_items, last_split = 0, first_local = n_items;
+    bool any_prep = false, any_split = false;
+    for (const PartDesc &p : pd) {
+        const bool big = p.m > (uint32_t)kLocalSlots;
+        const uint32_t nsplit = (p.m + kSplitPoints - 1) / kSplitPoints;
+        for (uint32_t i = 0; i < p.count; ++i) {
+            const uint32_t w = p.win0 + i;
+            if (big) {
+                const uint64_t off = (uint64_t)p.sorted0 + (uint64_t)i * p.m;
+                if (off + p.m > split)
+                    return fail("sorted range beyond total", (long)off, (long)split);
+                for (uint32_t j = 0; j < p.m; ++j)
+                    if (sorted_used[off + j]++)
+                        return fail("sorted ranges overlap", (long)w, (long)(off + j));
+                const uint32_t qp = p.prep0 + i;
+                if (qp >= n_items || queue[qp]++)
+                    return fail("prep entry", (long)qp, (long)n_items);
+                prepped[w]++;
+                last_prep = std::max(last_prep, qp);
+                any_prep = true;
+                for (uint32_t t = 0; t < nsplit; ++t) {
+                    const uint32_t qs = p.item0 + i * nsplit + t;
+                    if (qs >= n_items || queue[qs]++)
+                        return fail("split entry", (long)qs, (long)n_items);
+                    first_split = std::min(first_split, qs);
+                    last_split = std::max(last_split, qs);
+                    any_split = true;
+                }
+                covered[w]++;
+            } else if (i % p.per_item == 0) {
+                const uint32_t nw = std::min(p.per_item, p.count - i);
+                const uint32_t ql = p.item0 + i / p.per_item;
+                if (ql >= n_items || queue[ql]++)
+                    return fail("local entry", (long)ql, (long)n_items);
+                first_local = std::min(first_local, ql);
+                if (nw > (uint32_t)kLocalWindows || nw * ((p.m + 1u) & ~1u) > (uint32_t)kLocalSlots ||
+                    nw * plan_pow2(std::max(p.m, 2u)) > (uint32_t)kLocalSort)
+                    return fail("local item limits", (long)p.m, (long)nw);
+                for (uint32_t r = 0; r < nw; ++r)
+                    covered[w + r]++;
+            }
+        }
+    }
+    for (uint32_t q = 0; q < n_items; ++q)
+        if (queue[q] != 1)
+            return fail("queue entry not written once", (long)q, (long)queue[q]);
+    for (uint64_t w = 0; w < n_win; ++w)
+        if (covered[w] != 1)
+            return fail("window not covered once", (long)w, (long)covered[w]);
+    for (size_t j = 0; j < split; ++j)
+        if (sorted_used[j] != 1)
+            return fail("sorted point unused", (long)j, 0);
+    if ((any_prep && any_split && last_prep >= first_split) || (any_split && last_split >= first_local))
+        return fail("queue order prep < split < local", (long)last_prep, (long)first_local);
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
     int cases = argc > 1 ? std::atoi(argv[1]) : 300;
@@ -187,6 +263,18 @@ int main(int argc, char **argv)
                 std::printf("case %d style %d plain %d\n", c, style, plain);
                 return 1;
             }
+    }
+    for (int c = 0; c < cases; ++c) {
+        std::vector<PartDesc> pd(1 + rng() % 40);
+        for (PartDesc &p : pd) {
+            p = PartDesc{};
+            p.m = (rng() % 3 == 0) ? 1u << (5 + rng() % 8) : (uint32_t)(1 + rng() % 4096);
+            p.count = (uint32_t)(1 + rng() % 300);
+        }
+        if (check_parts(pd)) {
+            std::printf("parts case %d\n", c);
+            return 1;
+        }
     }
     std::printf("OK %d\n", cases);
     return 0;

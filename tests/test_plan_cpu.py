@@ -1,5 +1,6 @@
-"""The batch work list (csrc/wmi_plan.h) on random query mixes, on the CPU:
-coverage and the capacity limits the main kernel's LDS layout relies on."""
+"""The work lists (csrc/wmi_plan.h) on random inputs, on the CPU: coverage
+and the capacity limits the main kernel's LDS layout relies on, for batches
+and for serving launches."""
 import os
 import subprocess
 import tempfile
