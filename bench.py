@@ -13,8 +13,9 @@ with HIP events around each kernel; `value` is windows / (wall time / step).
 
 Also reported: the same steps as HIP-graph launches, the plain form (one
 prep + one main launch per window), end-to-end query latency (fresh submit ->
-results on host), the roofline of the main kernel and the CPU oracle on the
-host's cores.
+results on host), the roofline of the main kernel, the serving loop on 1024
+resident series of 2^20 points under a Poisson request stream (p50/p99
+latency, throughput) and the CPU oracle on the host's cores.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -35,6 +36,24 @@ METRIC = "window-MI evals/s and distance ops/s (% FP32 VALU peak); p50/p99 query
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test, 2 x (difference + compare)
+
+
+# HBM traffic of main_kernel<4> per launch on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), each scaled by what the
+# same counter reads for an elementwise kernel of known traffic (256 MiB read,
+# 256 MiB written): FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0.  Valid only for the
+# kernel source it was taken on (hash of the kernel and descriptor sources).
+TRAFFIC = {"kernel_sha256": "6cd24fc042cfe4917dc454b08f287b64555bb54beeda052d421a4307966fc749",
+           "fetch_bytes": 46027530, "write_bytes": 14401088}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wmi_kernels.hip", "wmi_internal.h"):
+        with open(os.path.join(ROOT, "paper_2204_09131_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -59,9 +78,115 @@ def cpu_baseline(workload, budget_s: float = 20.0) -> dict:
         if dt > 3.0 or step == 1 or t_used > budget_s:
             break
         step = max(1, step // 4)
+    # whole passes over the sample until about 10 s of work
+    reps = max(1, int(10.0 / max(dt, 1e-3)))
+    if reps > 1:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            orc.batch(workload.series, sub, k=workload.k)
+        dt = (time.perf_counter() - t0) / reps
     return {"value": len(sub) / dt, "unit": "window-MI evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sub)} of {len(q)} windows (every {step}-th, all scales), {dt:.2f} s",
+            "sample": f"{len(sub)} of {len(q)} windows (every {step}-th, all scales), "
+                      f"{reps} pass(es) of {dt:.2f} s each",
             "pairs_per_s": float(np.sum(sub['len'].astype(np.float64) * (sub['len'] - 1.0))) / dt}
+
+
+def serve_bench(args, torch, synth, wmi) -> dict:
+    """Serving workload: 1024 resident series x 2^20 points (4 GiB, cfg2
+    segment recipe, drawn on the device), a Poisson stream of range requests
+    (random pair, w log-uniform in [32, 2048], stride w/4, whole series) at
+    `rate` per second, continuous batching with arena admission.  Latency of a
+    request = results on the host minus its scheduled arrival.  Then the same
+    requests submitted at once (saturation throughput)."""
+    import threading
+    n_series, n = 1024, 1 << 20
+    t_gen = time.perf_counter()
+    data = synth.cfg2_pairs_device(n_series // 2, n, seed=4, device="cuda")
+    torch.cuda.synchronize()
+    log(f"serve: generated {n_series} x {n} series in {time.perf_counter() - t_gen:.1f} s")
+    t, a, b, w, stride = synth.config4_stream(n_queries=args.serve_queries, n_series=n_series, n=n,
+                                              rate=args.serve_rate)
+    st = wmi.Store(0)
+    ids = [st.add_series(data[i]) for i in range(n_series)]
+    assert ids == list(range(n_series))
+    pairs_of = w.astype(np.float64) * (w - 1) * ((n - w) // stride + 1)
+    wins_of = ((n - w) // stride + 1).astype(np.float64)
+
+    def run_stream(times, srv):
+        tickets = [0] * len(times)
+        sched = np.zeros(len(times))
+        errors = []
+
+        def producer():
+            try:
+                c0 = srv.clock_us()
+                for i in range(len(times)):
+                    due = c0 + times[i] * 1e6
+                    while True:
+                        now = srv.clock_us()
+                        if now >= due:
+                            break
+                        time.sleep(min(0.002, (due - now) * 1e-6))
+                    sched[i] = due
+                    tickets[i] = srv.submit(int(a[i]), int(b[i]), 0, n, int(w[i]), int(stride[i]))
+            except Exception as e:  # reported by the collector below
+                errors.append(e)
+
+        th = threading.Thread(target=producer)
+        w0 = time.perf_counter()
+        th.start()
+        lat = np.zeros(len(times))
+        done = 0
+        while done < len(times):
+            while tickets[done] == 0:
+                if errors:
+                    raise errors[0]
+                time.sleep(0.0005)
+            srv.wait(tickets[done], 600_000_000)
+            if done % 1000 == 999:
+                log(f"serve: {done + 1} of {len(times)} requests done")
+            res, info = srv.read(tickets[done])
+            if not np.all(np.isfinite(res["mi"])):
+                raise RuntimeError(f"request {done}: non-finite MI")
+            lat[done] = (info["t_complete_us"] - sched[done]) * 1e-3
+            done += 1
+        th.join()
+        return lat, time.perf_counter() - w0
+
+    out = {"workload": f"serving: {n_series} resident series x {n} float32 (cfg2 segment recipe), "
+                       "Poisson range requests (random pair, w log-uniform 32..2048, stride w/4, whole series)",
+           "k": 4}
+    with wmi.Server(st, k=4) as srv:
+        # warm up the scheduler and both launch slots
+        lat_w, _ = run_stream(np.zeros(8), srv)
+        q = args.serve_queries
+        lat, wall = run_stream(t[:q], srv)
+        stats = srv.stats()
+    out["poisson"] = {"rate_qps": args.serve_rate, "queries": int(q), "wall_s": wall,
+                      "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                      "max_ms": float(lat.max()), "throughput_qps": q / wall,
+                      "windows_per_s": float(wins_of[:q].sum() / wall),
+                      "pairs_per_s": float(pairs_of[:q].sum() / wall),
+                      "launches": int(stats["launches"]), "gpu_busy_frac": stats["busy_us"] * 1e-6 / wall,
+                      "arena_peak_bytes": int(stats["arena_peak_bytes"]),
+                      "queued_peak": int(stats["queued_peak"])}
+    log(f"serve poisson: {out['poisson']}")
+    # saturation: the first requests of the stream, all arriving at once
+    qs = min(args.serve_queries, args.serve_burst)
+    with wmi.Server(st, k=4) as srv:
+        run_stream(np.zeros(8), srv)
+        lat_s, wall_s = run_stream(np.zeros(qs), srv)
+        stats = srv.stats()
+    out["saturation"] = {"queries": int(qs), "wall_s": wall_s, "throughput_qps": qs / wall_s,
+                         "windows_per_s": float(wins_of[:qs].sum() / wall_s),
+                         "pairs_per_s": float(pairs_of[:qs].sum() / wall_s),
+                         "p50_ms": float(np.percentile(lat_s, 50)), "p99_ms": float(np.percentile(lat_s, 99)),
+                         "gpu_busy_frac": stats["busy_us"] * 1e-6 / wall_s, "launches": int(stats["launches"])}
+    log(f"serve saturation: {out['saturation']}")
+    st.close()
+    del data
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -72,6 +197,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
+    ap.add_argument("--serve-queries", type=int, default=3000,
+                    help="requests of the Poisson serving stream (20000 = the full stream)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-burst", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -160,10 +290,12 @@ def main():
         log(f"plain: {p_ms:.1f} ms/step")
 
     if args.copy_calibration:
-        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        # an elementwise kernel of known traffic (reads 256 MiB, writes 256 MiB)
+        # that HBM byte counters are scaled by
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
 
     st.close()
@@ -194,10 +326,14 @@ def main():
         "kernels_ms": {"main": tim["main_ms"], "prep": tim["prep_ms"], "runs": tim["runs"]},
         "roofline": {"bound": "alu", "kernel": "main_kernel<4>", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None,
+                     "traffic": (TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+                                 if kernel_source_hash() == TRAFFIC["kernel_sha256"] else None),
+                     "traffic_unit": "HBM bytes per launch (fetch + write, calibrated counters)",
                      "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs},
         "plain_gpu": plain,
     }
+    if not args.no_serve:
+        out["serving"] = serve_bench(args, torch, synth, wmi)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -204,6 +204,41 @@ def config4_pair(pair_id: int, n: int = 1 << 20):
     return cfg2_pair(n, 4 + pair_id)
 
 
+def _quantize_torch(v):
+    import torch
+    q = torch.clamp(torch.round(v * GRID), -QMAX, QMAX)
+    return (q / GRID).to(torch.float32)
+
+
+def cfg2_pairs_device(n_pairs: int, n: int, seed: int, device, chunk: int = 16):
+    """The cfg2 segment recipe drawn with torch's generator on `device`: a
+    (2 * n_pairs, n) float32 tensor, rows (x0, y0, x1, y1, ...).  Used where
+    host generation would take minutes (the serving store: 512 pairs of 2^20
+    points).  Deterministic for a seed on a given device and torch build; not
+    the same numbers as ``cfg2_pair``."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty((2 * n_pairs, n), dtype=torch.float32, device=device)
+    nseg = n // 256 + 2
+    pos = torch.arange(n, device=device)
+    for p0 in range(0, n_pairs, chunk):
+        c = min(chunk, n_pairs - p0)
+        x = _quantize_torch(torch.randn((c, n), generator=g, device=device, dtype=torch.float64))
+        e = _quantize_torch(torch.randn((c, n), generator=g, device=device, dtype=torch.float64))
+        lens = torch.randint(256, 4097, (c, nseg), generator=g, device=device)
+        ends = torch.cumsum(lens, dim=1)
+        kind = torch.searchsorted(ends, pos.expand(c, n).contiguous(), right=True) % 4
+        xd, ed = x.double(), e.double()
+        y = torch.where(kind == 0, 0.8 * xd + 0.6 * ed,
+                        torch.where(kind == 1, xd * xd + 0.3 * ed,
+                                    torch.where(kind == 2, torch.sin(3.0 * xd) + 0.3 * ed, ed)))
+        out[2 * p0:2 * (p0 + c):2] = x
+        out[2 * p0 + 1:2 * (p0 + c):2] = _quantize_torch(y)
+        del x, e, xd, ed, y, kind, lens, ends
+    return out
+
+
 def config4_stream(n_queries: int = 20000, n_series: int = 1024, n: int = 1 << 20,
                    rate: float = 200.0, wmin: int = 32, wmax: int = 2048, seed: int = 4):
     """Poisson arrivals; each query = (a, b, w, stride=w//4) over the full series."""
