@@ -2,23 +2,25 @@
 //
 // HBM layout of one launch (all arrays carved from one batch allocation):
 //   WinDesc  win[W]      one per window (a noise triple contributes three)
-//   Item     item[I]     work items, largest first: a split item is one block
-//                        of query points of a window above kLocalSlots points;
-//                        a local item is up to kLocalWindows consecutive
-//                        windows (whole queries where they fit) done entirely
-//                        inside one workgroup
-//   u32      prep[Np]    the split windows; their marginals are sorted by prep
-//                        items at the head of the queue (plain form: by the
-//                        prep kernel); local items sort in LDS
+//   Item     item[I]     the work queue: prep items first (sort a split
+//                        window's marginals), then split items (one block of
+//                        query points of a window above kLocalSlots points)
+//                        and local items (up to kLocalWindows consecutive
+//                        windows done entirely inside one workgroup), larger
+//                        work first
+//   u32      prep[Np]    the split windows (plain form: sorted by the prep
+//                        kernel, one launch per window)
 //   u32      ready[W]    per window: sorted marginals written
 //   QDesc    qd[Qn]      one per query: its first window, window count, tau
-//   int32    sorted[2*P] per window, its x and y grid integers in ascending
-//                        order (P = sum of m); written by the prep kernel
-//   WinAux   aux[W]      per window: grid minima, key width, off-grid flag
+//   int32    sorted[2*P] per split window, its x and y grid integers in
+//                        ascending order (P = sum of their m)
 //   u64      acc[W]      fixed-point digamma sums (2^-44), integer atomics
 //   u32      wdone[W], qdone[Qn], counter[1]   completion and work counters
 //   double   wmi[W]; u32 wflags[W]           per-window estimate and flags
 //   Result   res[Qn]     32-byte results, copied back to the host
+// A serving launch has the same arrays (one window per query) and writes
+// CompactResult records into request slices of the server's arena instead
+// of res.
 #pragma once
 #include <stdint.h>
 
@@ -61,7 +63,7 @@ struct QDesc {              // 16 bytes
     double tau_eff;         // noise threshold, already normalised if requested
 };
 
-struct WinAux {             // 16 bytes
+struct WinAux {             // per split item, computed by the item itself
     int32_t min_x, min_y;   // window minima of the grid integers
     uint32_t nb;            // index bits in a 32-bit key; 0 selects 64-bit keys
     uint32_t flags;         // kFlagOffGrid
@@ -102,7 +104,6 @@ struct LaunchArgs {
     const Item *item;
     const QDesc *qd;
     int32_t *sorted;
-    WinAux *aux;
     unsigned long long *acc;
     uint32_t *wdone;
     uint32_t *qdone;

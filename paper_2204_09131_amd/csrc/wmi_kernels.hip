@@ -18,10 +18,13 @@
 //               neighbours, sorts each window's marginals in LDS (bitonic),
 //               counts by binary search, sums digamma terms with LDS integer
 //               atomics and writes the results: no global atomics, no fences.
-//   split item  512 query points of a window above 512 points.  The prep
-//               kernel sorts such windows' marginals into HBM beforehand;
-//               items add exact fixed-point digamma sums with integer
-//               atomics and the last item of a window forms its estimate.
+//   split item  512 query points of a window above 512 points.  A prep
+//               item at the head of the same queue sorts the window's
+//               marginals into HBM (the plain form launches a prep kernel
+//               instead); a split item finds its neighbours first and waits
+//               (bounded) for that sort only before counting.  Items add
+//               exact fixed-point digamma sums with integer atomics and the
+//               last item of a window forms its estimate.
 //
 // Neighbour search.  Each lane owns query points and scans all m candidates
 // of its window from LDS, keeping the k+1 smallest 32-bit keys in registers
@@ -306,17 +309,13 @@ __device__ __forceinline__ long long count_terms(const LaunchArgs &a, const int3
     return a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
 }
 
-// Neighbours of one query from its k+1 smallest keys: drop the point itself
-// (key i: distance 0, index i), then the radii in grid units.
+// Radii of one query (grid units) from the keys of its k neighbours; the
+// neighbours' coordinates are read back from the window's keys in LDS.
 template <int K, typename T>
-__device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, int shift, uint32_t mask, int m,
-                                                const uint32_t *cand, uint32_t base, uint32_t qx, uint32_t qy,
-                                                int dshift, uint32_t est, uint32_t &rx, uint32_t &ry)
+__device__ __forceinline__ void radii_k(const T (&nbk)[K], int shift, uint32_t mask, int m, const uint32_t *cand,
+                                        uint32_t base, uint32_t qx, uint32_t qy, int dshift, uint32_t est,
+                                        uint32_t &rx, uint32_t &ry)
 {
-    T nbk[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r)
-        nbk[r] = top[r] < self ? top[r] : top[r + 1];
     if (est == 0) {
         uint32_t ex = 0, ey = 0;
 #pragma unroll
@@ -333,6 +332,20 @@ __device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, i
         rx = (uint32_t)(nbk[K - 1] >> shift);
         ry = rx;
     }
+}
+
+// Same from the k+1 smallest keys of a scan that included the point itself
+// (its key is self: distance 0, index i), which is dropped first.
+template <int K, typename T>
+__device__ __forceinline__ void radii_from_keys(const T (&top)[K + 1], T self, int shift, uint32_t mask, int m,
+                                                const uint32_t *cand, uint32_t base, uint32_t qx, uint32_t qy,
+                                                int dshift, uint32_t est, uint32_t &rx, uint32_t &ry)
+{
+    T nbk[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        nbk[r] = top[r] < self ? top[r] : top[r + 1];
+    radii_k<K, T>(nbk, shift, mask, m, cand, base, qx, qy, dshift, est, rx, ry);
 }
 
 // --------------------------------------------------------------------------
@@ -732,69 +745,123 @@ struct LocalShared {
     uint32_t P, log2P;
 };
 
-// One slot's neighbour search inside a local item.  mode 0: every active lane
-// of the wave has the same m and 32-bit keys; 1: 32-bit keys, lanes with
-// different m (masked); 2: 64-bit keys.  m_loop is the wave's largest m.
+// Scan candidates [jlo, jhi) of one window (cand: its keys, two words per
+// point, jlo even) for a thread's two consecutive query points (slot 2t and
+// 2t+1: points self and self+1, self even) into S-entry lists t0, t1.
+// MASKM: j >= m is padding beyond this lane's window (the loop runs to the
+// wave's longest window); SELF: the queries' own points are masked (keys set
+// to the maximum) so k-entry lists hold neighbours only.
+template <int S, bool MASKM, bool SELF>
+__device__ __forceinline__ void local_scan2(const uint32_t *__restrict__ cand, int jlo, int jhi, int m, uint32_t self,
+                                            uint32_t qx0, uint32_t qy0, uint32_t qx1, uint32_t qy1,
+                                            uint32_t (&t0)[S], uint32_t (&t1)[S])
+{
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(cand);
+    int j = jlo;
+    for (; j + 1 < jhi; j += 2) {
+        const uint4 c = c4[j >> 1];
+        const uint32_t j0 = (uint32_t)j;
+        uint32_t a0 = tmax(sad_key(qx0, c.x, j0), sad_key(qy0, c.y, j0));
+        uint32_t a1 = tmax(sad_key(qx0, c.z, j0 + 1u), sad_key(qy0, c.w, j0 + 1u));
+        uint32_t b0 = tmax(sad_key(qx1, c.x, j0), sad_key(qy1, c.y, j0));
+        uint32_t b1 = tmax(sad_key(qx1, c.z, j0 + 1u), sad_key(qy1, c.w, j0 + 1u));
+        if (MASKM) {
+            a0 = (int)j0 < m ? a0 : 0xFFFFFFFFu;
+            b0 = (int)j0 < m ? b0 : 0xFFFFFFFFu;
+            a1 = (int)j0 + 1 < m ? a1 : 0xFFFFFFFFu;
+            b1 = (int)j0 + 1 < m ? b1 : 0xFFFFFFFFu;
+        }
+        if (SELF) {
+            // j0 even: only (query 0, j0 == self) and (query 1, j0 + 1 == self + 1)
+            const bool hit = j0 == self;
+            a0 = hit ? 0xFFFFFFFFu : a0;
+            b1 = hit ? 0xFFFFFFFFu : b1;
+        }
+        insert_sorted<S>(t0, a0);
+        insert_sorted<S>(t0, a1);
+        insert_sorted<S>(t1, b0);
+        insert_sorted<S>(t1, b1);
+    }
+    if (j < jhi) {
+        const uint32_t cx = cand[2 * j], cy = cand[2 * j + 1], j0 = (uint32_t)j;
+        uint32_t a0 = tmax(sad_key(qx0, cx, j0), sad_key(qy0, cy, j0));
+        uint32_t b0 = tmax(sad_key(qx1, cx, j0), sad_key(qy1, cy, j0));
+        if (MASKM) {
+            a0 = (int)j0 < m ? a0 : 0xFFFFFFFFu;
+            b0 = (int)j0 < m ? b0 : 0xFFFFFFFFu;
+        }
+        if (SELF) {
+            a0 = j0 == self ? 0xFFFFFFFFu : a0;
+            b0 = j0 == self + 1u ? 0xFFFFFFFFu : b0;
+        }
+        insert_sorted<S>(t0, a0);
+        insert_sorted<S>(t1, b0);
+    }
+}
+
+// Neighbour search of a thread's two slots inside a local item (points i0
+// and i0 + 1 of the window at slot offset base).  Wave-uniform mode:
+//   0  the whole wave is inside one window (32-bit keys): k-entry lists,
+//      the points themselves masked inside the wave's band of 128 points
+//   1  lanes in several windows of the same m (32-bit keys): k+1 entries,
+//      the point itself dropped at the end
+//   2  lanes in windows of different m (32-bit keys): as 1, candidates past
+//      a lane's own window masked
+//   3  some window needs 64-bit keys: one slot at a time
+// m_loop is the wave's longest window; band0 (mode 0) its first point.
 template <int K>
-__device__ __forceinline__ void local_knn(const uint32_t *__restrict__ cand, uint32_t base, int m, int i,
-                                          uint32_t nb, int mode, int m_loop, uint32_t est, uint32_t &rx,
-                                          uint32_t &ry)
+__device__ __forceinline__ void local_knn2(const uint32_t *__restrict__ cand, uint32_t base, int m, int i0,
+                                           uint32_t nb, int mode, int m_loop, int band0, uint32_t est,
+                                           uint32_t (&rx)[2], uint32_t (&ry)[2])
 {
     constexpr int S = K + 1;
-    const uint32_t qx = cand[2 * (base + i)], qy = cand[2 * (base + i) + 1];
-    const uint4 *c4 = reinterpret_cast<const uint4 *>(cand + 2 * base);
+    const uint32_t *cw = cand + 2 * base;
+    const uint32_t qx0 = cw[2 * i0], qy0 = cw[2 * i0 + 1];
+    const uint32_t qx1 = cw[2 * i0 + 2], qy1 = cw[2 * i0 + 3];
+    const uint32_t mask = (1u << nb) - 1u;
     if (mode == 0) {
-        uint32_t top[S];
+        uint32_t t0[K], t1[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            t0[r] = t1[r] = 0xFFFFFFFFu;
+        const int b1 = min(band0 + 128, m_loop);
+        local_scan2<K, false, false>(cw, 0, band0, m, (uint32_t)i0, qx0, qy0, qx1, qy1, t0, t1);
+        local_scan2<K, false, true>(cw, band0, b1, m, (uint32_t)i0, qx0, qy0, qx1, qy1, t0, t1);
+        local_scan2<K, false, false>(cw, b1, m_loop, m, (uint32_t)i0, qx0, qy0, qx1, qy1, t0, t1);
+        radii_k<K, uint32_t>(t0, (int)nb, mask, m, cand, base, qx0, qy0, (int)nb, est, rx[0], ry[0]);
+        radii_k<K, uint32_t>(t1, (int)nb, mask, m, cand, base, qx1, qy1, (int)nb, est, rx[1], ry[1]);
+    } else if (mode == 1 || mode == 2) {
+        uint32_t t0[S], t1[S];
 #pragma unroll
         for (int r = 0; r < S; ++r)
-            top[r] = 0xFFFFFFFFu;
-        int j = 0;
-        for (; j + 1 < m_loop; j += 2) {
-            uint4 c = c4[j >> 1];
-            insert_sorted<S>(top, tmax(sad_key(qx, c.x, (uint32_t)j), sad_key(qy, c.y, (uint32_t)j)));
-            insert_sorted<S>(top, tmax(sad_key(qx, c.z, (uint32_t)j + 1u), sad_key(qy, c.w, (uint32_t)j + 1u)));
-        }
-        if (j < m_loop) {
-            uint32_t cx = cand[2 * (base + j)], cy = cand[2 * (base + j) + 1];
-            insert_sorted<S>(top, tmax(sad_key(qx, cx, (uint32_t)j), sad_key(qy, cy, (uint32_t)j)));
-        }
-        radii_from_keys<K, uint32_t>(top, (uint32_t)i, (int)nb, (1u << nb) - 1u, m, cand, base, qx, qy, (int)nb, est,
-                                     rx, ry);
-    } else if (mode == 1) {
-        uint32_t top[S];
-#pragma unroll
-        for (int r = 0; r < S; ++r)
-            top[r] = 0xFFFFFFFFu;
-        int j = 0;
-        for (; j + 1 < m_loop; j += 2) {
-            uint4 c = c4[j >> 1];
-            uint32_t k0 = tmax(sad_key(qx, c.x, (uint32_t)j), sad_key(qy, c.y, (uint32_t)j));
-            uint32_t k1 = tmax(sad_key(qx, c.z, (uint32_t)j + 1u), sad_key(qy, c.w, (uint32_t)j + 1u));
-            insert_sorted<S>(top, j < m ? k0 : 0xFFFFFFFFu);
-            insert_sorted<S>(top, j + 1 < m ? k1 : 0xFFFFFFFFu);
-        }
-        if (j < m_loop) {
-            uint32_t cx = cand[2 * (base + j)], cy = cand[2 * (base + j) + 1];
-            uint32_t k0 = tmax(sad_key(qx, cx, (uint32_t)j), sad_key(qy, cy, (uint32_t)j));
-            insert_sorted<S>(top, j < m ? k0 : 0xFFFFFFFFu);
-        }
-        radii_from_keys<K, uint32_t>(top, (uint32_t)i, (int)nb, (1u << nb) - 1u, m, cand, base, qx, qy, (int)nb, est,
-                                     rx, ry);
+            t0[r] = t1[r] = 0xFFFFFFFFu;
+        if (mode == 1)
+            local_scan2<S, false, false>(cw, 0, m_loop, m, (uint32_t)i0, qx0, qy0, qx1, qy1, t0, t1);
+        else
+            local_scan2<S, true, false>(cw, 0, m_loop, m, (uint32_t)i0, qx0, qy0, qx1, qy1, t0, t1);
+        radii_from_keys<K, uint32_t>(t0, (uint32_t)i0, (int)nb, mask, m, cand, base, qx0, qy0, (int)nb, est, rx[0],
+                                     ry[0]);
+        radii_from_keys<K, uint32_t>(t1, (uint32_t)i0 + 1u, (int)nb, mask, m, cand, base, qx1, qy1, (int)nb, est,
+                                     rx[1], ry[1]);
     } else {
-        unsigned long long top[S];
 #pragma unroll
-        for (int r = 0; r < S; ++r)
-            top[r] = ~0ull;
-        const uint32_t px = qx >> nb, py = qy >> nb;
-        for (int j = 0; j < m_loop; ++j) {
-            uint32_t cx = cand[2 * (base + j)] >> nb, cy = cand[2 * (base + j) + 1] >> nb;
-            uint32_t d = tmax(sad_u32(px, cx, 0u), sad_u32(py, cy, 0u));
-            unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
-            if (j < m && key < top[S - 1])
-                insert_sorted<S>(top, key);
+        for (int q = 0; q < 2; ++q) {
+            const int i = i0 + q;
+            unsigned long long top[S];
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                top[r] = ~0ull;
+            const uint32_t px = cw[2 * i] >> nb, py = cw[2 * i + 1] >> nb;
+            for (int j = 0; j < m_loop; ++j) {
+                uint32_t cx = cw[2 * j] >> nb, cy = cw[2 * j + 1] >> nb;
+                uint32_t d = tmax(sad_u32(px, cx, 0u), sad_u32(py, cy, 0u));
+                unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
+                if (j < m && key < top[S - 1])
+                    insert_sorted<S>(top, key);
+            }
+            radii_from_keys<K, unsigned long long>(top, (unsigned long long)i, 12, 0xFFFu, m, cand, base,
+                                                   cw[2 * i], cw[2 * i + 1], (int)nb, est, rx[q], ry[q]);
         }
-        radii_from_keys<K, unsigned long long>(top, (unsigned long long)i, 12, 0xFFFu, m, cand, base, qx, qy,
-                                               (int)nb, est, rx, ry);
     }
 }
 
@@ -841,9 +908,10 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     uint32_t W[2];
     int I[2];
     bool act[2];
+    // slots 2t and 2t+1: window offsets are even, so both lie in one window
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const uint32_t s = (uint32_t)tid + (uint32_t)(q * kBlock);
+        const uint32_t s = 2u * (uint32_t)tid + (uint32_t)q;
         uint32_t w = 0;
         while (w + 1 < nwin && L.off[w + 1] <= s)
             ++w;
@@ -887,7 +955,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (act[q]) {
-            const uint32_t s = (uint32_t)tid + (uint32_t)(q * kBlock);
+            const uint32_t s = 2u * (uint32_t)tid + (uint32_t)q;
             const uint32_t w = W[q], nb = L.nb[w];
             cand[2 * s] = (uint32_t)(X[q] - L.mn[0][w]) << nb;
             cand[2 * s + 1] = (uint32_t)(Y[q] - L.mn[1][w]) << nb;
@@ -895,33 +963,39 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     }
     __syncthreads();
 
-    // ---- neighbours: one pass per slot of the thread
+    // ---- neighbours: one pass over the window for both slots of the thread
     uint32_t RX[2] = {0u, 0u}, RY[2] = {0u, 0u};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const bool live = act[q] && (int)L.m[W[q]] > K;
+    {
+        // slot 2t+1 is live only if slot 2t is (a pad slot is always the second)
+        const bool live = act[0] && (int)L.m[W[0]] > K;
         const unsigned long long bal = __ballot(live);
-        if (bal == 0ull)
-            continue;  // wave-uniform
-        // lanes without a live slot follow the first live lane's window
-        const int first = __ffsll((long long)bal) - 1;
-        const uint32_t lead_w = (uint32_t)__shfl((int)W[q], first, 64);
-        const uint32_t wl = live ? W[q] : lead_w;
-        const int il = live ? I[q] : 0;
-        const int m = (int)L.m[wl];
-        const uint32_t nb = L.nb[wl];
-        // wave-wide: same m everywhere?  any 64-bit window?  largest m?
-        int m_max = m, m_min = m;
-        uint32_t nb_min = nb;
-        for (int o = 32; o > 0; o >>= 1) {
-            m_max = max(m_max, __shfl_xor(m_max, o, 64));
-            m_min = min(m_min, __shfl_xor(m_min, o, 64));
-            nb_min = min(nb_min, (uint32_t)__shfl_xor((int)nb_min, o, 64));
+        if (bal != 0ull) {  // wave-uniform
+            // lanes without a live slot follow the first live lane's window
+            const int first = __ffsll((long long)bal) - 1;
+            const uint32_t lead_w = (uint32_t)__shfl((int)W[0], first, 64);
+            const int lead_i = __shfl(I[0], first, 64);
+            const uint32_t wl = live ? W[0] : lead_w;
+            const int il = live ? I[0] : lead_i;
+            const int m = (int)L.m[wl];
+            const uint32_t nb = L.nb[wl];
+            // wave-wide: one window?  same m everywhere?  any 64-bit window?
+            int m_max = m, m_min = m, w_min = (int)wl, w_max = (int)wl, i_min = il;
+            uint32_t nb_min = nb;
+            for (int o = 32; o > 0; o >>= 1) {
+                m_max = max(m_max, __shfl_xor(m_max, o, 64));
+                m_min = min(m_min, __shfl_xor(m_min, o, 64));
+                w_min = min(w_min, __shfl_xor(w_min, o, 64));
+                w_max = max(w_max, __shfl_xor(w_max, o, 64));
+                i_min = min(i_min, __shfl_xor(i_min, o, 64));
+                nb_min = min(nb_min, (uint32_t)__shfl_xor((int)nb_min, o, 64));
+            }
+            // the reductions leave the same value in every lane: make that explicit
+            m_max = __builtin_amdgcn_readfirstlane(m_max);
+            const int band0 = __builtin_amdgcn_readfirstlane(i_min);
+            const int mode = __builtin_amdgcn_readfirstlane(
+                nb_min == 0u ? 3 : (w_min == w_max ? 0 : (m_max == m_min ? 1 : 2)));
+            local_knn2<K>(cand, L.off[wl], m, il, nb, mode, m_max, band0, a.estimator, RX, RY);
         }
-        // the reductions leave the same value in every lane: make that explicit
-        m_max = __builtin_amdgcn_readfirstlane(m_max);
-        const int mode = __builtin_amdgcn_readfirstlane(nb_min == 0u ? 2 : (m_max == m_min ? 0 : 1));
-        local_knn<K>(cand, L.off[wl], m, il, nb, mode, m_max, a.estimator, RX[q], RY[q]);
     }
     __syncthreads();
 
@@ -1034,7 +1108,11 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
         if (itm.info & kItemLocal) {
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
         } else if (itm.info & kItemPrep) {
+            // a sort that split items of the window will wait for: its waves
+            // issue ahead of theirs
+            __builtin_amdgcn_s_setprio(3);
             prep_item(a, itm.win, buf);
+            __builtin_amdgcn_s_setprio(0);
         } else {
             // split items are the largest, taken first: let their waves issue
             // ahead of the short local items sharing the CU, so they are not
