@@ -61,6 +61,16 @@ __device__ __forceinline__ uint32_t sad_key(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
+// Workgroup barrier after this wave's LDS accesses have completed.  The
+// wait is explicit: the compiler's own wait before a barrier at the head of
+// a loop (reached along the back edge from LDS stores) was found missing, and
+// stores still in flight then raced with other waves' loads.
+__device__ __forceinline__ void block_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T>
@@ -145,8 +155,58 @@ __global__ void clear_kernel(LaunchArgs a)
 // prep: sorted marginals of a split window (one workgroup)
 // --------------------------------------------------------------------------
 
-// Sort the grid integers of one coordinate of a window into out[0..m),
-// bitonic in LDS (P = next power of two >= m entries of scratch).
+// Ascending bitonic sort in LDS of `total` entries of array a (and of b, if
+// NA == 2), as segments of P entries each (P a power of two dividing total,
+// total <= 2 * R * kBlock).  Each stage pairs entry lo with lo + stride; a
+// thread takes pairs tid + r * kBlock and loads all of them before any
+// compare, so their LDS latencies overlap.  A workgroup barrier precedes
+// every stage.  Called by the whole workgroup; ends with a barrier.
+template <int R, int NA>
+__device__ void bitonic_lds(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t npairs = total >> 1;
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            block_sync();
+            int32_t va[R][2], vb[R][2];
+            uint32_t lo[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t t = tid + (uint32_t)(r * kBlock);
+                lo[r] = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u));
+                if (t < npairs) {
+                    va[r][0] = a[lo[r]];
+                    va[r][1] = a[lo[r] + stride];
+                    if (NA == 2) {
+                        vb[r][0] = b[lo[r]];
+                        vb[r][1] = b[lo[r] + stride];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t t = tid + (uint32_t)(r * kBlock);
+                if (t < npairs) {
+                    // direction from the index inside the segment: every segment ascends
+                    const bool asc = ((lo[r] & (P - 1u)) & size) == 0u;
+                    const int32_t mn = min(va[r][0], va[r][1]), mx = max(va[r][0], va[r][1]);
+                    a[lo[r]] = asc ? mn : mx;
+                    a[lo[r] + stride] = asc ? mx : mn;
+                    if (NA == 2) {
+                        const int32_t nn = min(vb[r][0], vb[r][1]), nx = max(vb[r][0], vb[r][1]);
+                        b[lo[r]] = asc ? nn : nx;
+                        b[lo[r] + stride] = asc ? nx : nn;
+                    }
+                }
+            }
+        }
+    }
+    block_sync();
+}
+
+// Sort the grid integers of one coordinate of a window into out[0..m)
+// (P = next power of two >= m entries of scratch, P <= kMaxWindow).
 __device__ void sort_marginal(const float *v, int m, int32_t *scratch, int32_t *out)
 {
     const int tid = threadIdx.x;
@@ -154,27 +214,13 @@ __device__ void sort_marginal(const float *v, int m, int32_t *scratch, int32_t *
     while (P < m)
         P <<= 1;
     uint32_t off = 0;
+    block_sync();
     for (int i = tid; i < P; i += kBlock)
         scratch[i] = i < m ? grid_int(v[i], off) : INT32_MAX;
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int t = tid; t < (P >> 1); t += kBlock) {
-                const int lo = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const int32_t a0 = scratch[lo], a1 = scratch[hi];
-                if ((a0 > a1) == asc) {
-                    scratch[lo] = a1;
-                    scratch[hi] = a0;
-                }
-            }
-        }
-    }
-    __syncthreads();
+    bitonic_lds<kMaxWindow / (2 * kBlock), 1>(scratch, nullptr, (uint32_t)P, (uint32_t)P);
     for (int i = tid; i < m; i += kBlock)
         out[i] = scratch[i];
-    __syncthreads();
+    block_sync();
 }
 
 // Write the sorted marginals of window w to HBM, make them visible to every
@@ -188,7 +234,7 @@ __device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf)
     sort_marginal(d.x, m, scratch, out);
     sort_marginal(d.y, m, scratch, out + m);
     __threadfence();  // release: this wave's stores reach every XCD before the flag
-    __syncthreads();
+    block_sync();
     if (threadIdx.x == 0)
         atomicExch(&a.ready[w], 1u);
 }
@@ -365,7 +411,7 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
         s_red[3] = INT32_MIN;
         s_red[4] = 0;
     }
-    __syncthreads();
+    block_sync();
     int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
     uint32_t off = 0;
     for (int i = tid; i < m; i += kBlock) {
@@ -390,7 +436,7 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
         if (off)
             atomicOr(&s_red[4], 1);
     }
-    __syncthreads();
+    block_sync();
     WinAux ax;
     ax.min_x = s_red[0];
     ax.min_y = s_red[2];
@@ -400,7 +446,7 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
     // 32-bit keys need (range << nb) + j < 2^32
     ax.nb = (((rx | ry) >> (32 - nb)) == 0u) ? nb : 0u;
     ax.flags = s_red[4] ? kFlagOffGrid : 0u;
-    __syncthreads();
+    block_sync();
     return ax;
 }
 
@@ -420,7 +466,7 @@ __device__ void wait_ready(const LaunchArgs &a, uint32_t w)
             __builtin_amdgcn_s_sleep(8);
         }
     }
-    __syncthreads();
+    block_sync();
     __threadfence();  // acquire: later loads see the prep item's stores
 }
 
@@ -572,12 +618,12 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
         const int band1 = band0 + kBlock;
         for (int c0 = 0; c0 < m; c0 += kChunk) {
             const int cn = min(kChunk, m - c0), e = c0 + cn;
-            __syncthreads();
+            block_sync();
             for (int i = tid; i < cn; i += kBlock) {
                 buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, nb);
                 buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, nb);
             }
-            __syncthreads();
+            block_sync();
             scan_seg<K, Q, -1>(buf, c0, c0, min(e, band0), qx, qy, self, top);
             scan_seg<K, Q, 0>(buf, c0, max(c0, band0), min(e, band0 + 64), qx, qy, self, top);
             if (Q == 1) {
@@ -601,12 +647,12 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
                 top[q][r] = ~0ull;
         for (int c0 = 0; c0 < m; c0 += kChunk) {
             const int cn = min(kChunk, m - c0);
-            __syncthreads();
+            block_sync();
             for (int i = tid; i < cn; i += kBlock) {
                 buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, 0u);
                 buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, 0u);
             }
-            __syncthreads();
+            block_sync();
             scan_wide<K, Q>(buf, c0, cn, qx, qy, top);
         }
 #pragma unroll
@@ -630,12 +676,12 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
     const bool strict = a.estimator != 0;
     for (int c0 = 0; c0 < m; c0 += kChunk) {
         const int cn = min(kChunk, m - c0);
-        __syncthreads();
+        block_sync();
         for (int i = tid; i < cn; i += kBlock) {
             sx[i] = src[c0 + i];
             sy[i] = src[m + c0 + i];
         }
-        __syncthreads();
+        block_sync();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int32_t ex = (int32_t)rx[q], ey = (int32_t)ry[q];
@@ -700,7 +746,7 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *bu
         part += __shfl_xor(part, o, 64);
     if ((tid & 63) == 0)
         s_part[tid >> 6] = part;
-    __syncthreads();
+    block_sync();
     if (tid == 0) {
         long long tot = 0;
         for (int wv = 0; wv < kBlock / 64; ++wv)
@@ -886,7 +932,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         L.mx[0][tid] = INT32_MIN;
         L.mx[1][tid] = INT32_MIN;
     }
-    __syncthreads();
+    block_sync();
     if (tid == 0) {
         uint32_t off = 0, mmax = 2;
         for (uint32_t w = 0; w < nwin; ++w) {
@@ -899,7 +945,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         L.P = 1u << lp;
         L.log2P = lp;
     }
-    __syncthreads();
+    block_sync();
     const uint32_t total = L.off[nwin];
     const uint32_t P = L.P, lp = L.log2P;
 
@@ -942,7 +988,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             srt_y[t] = INT32_MAX;
         }
     }
-    __syncthreads();
+    block_sync();
     if (tid < (int)nwin) {
         const uint32_t m = L.m[tid];
         const uint32_t nb = ceil_log2(m > 1 ? m : 2u);
@@ -950,7 +996,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         const uint32_t ryr = (uint32_t)(L.mx[1][tid] - L.mn[1][tid]);
         L.nb[tid] = (((rxr | ryr) >> (32 - nb)) == 0u) ? nb : 0u;
     }
-    __syncthreads();
+    block_sync();
     // ---- keys (or X - min for the 64-bit path), by slot
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -961,7 +1007,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             cand[2 * s + 1] = (uint32_t)(Y[q] - L.mn[1][w]) << nb;
         }
     }
-    __syncthreads();
+    block_sync();
 
     // ---- neighbours: one pass over the window for both slots of the thread
     uint32_t RX[2] = {0u, 0u}, RY[2] = {0u, 0u};
@@ -997,31 +1043,10 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             local_knn2<K>(cand, L.off[wl], m, il, nb, mode, m_max, band0, a.estimator, RX, RY);
         }
     }
-    __syncthreads();
+    block_sync();
 
     // ---- sort every window's marginals (segments of P, padded with INT32_MAX)
-    const uint32_t npairs = (nwin << lp) >> 1;
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = tid; t < npairs; t += kBlock) {
-                const uint32_t lo = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u));
-                const uint32_t hi = lo + stride;
-                // direction from the index inside the segment: every segment ascends
-                const bool asc = ((lo & (P - 1u)) & size) == 0u;
-                int32_t a0 = srt_x[lo], a1 = srt_x[hi];
-                if ((a0 > a1) == asc) {
-                    srt_x[lo] = a1;
-                    srt_x[hi] = a0;
-                }
-                int32_t b0 = srt_y[lo], b1 = srt_y[hi];
-                if ((b0 > b1) == asc) {
-                    srt_y[lo] = b1;
-                    srt_y[hi] = b0;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, nwin << lp, P);
 
     // ---- counts and digamma terms
 #pragma unroll
@@ -1043,7 +1068,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             a.dbg_ey[I[q]] = (float)RY[q] * (1.0f / 4096.0f);
         }
     }
-    __syncthreads();
+    block_sync();
 
     // ---- estimates, then results
     if (tid < (int)nwin) {
@@ -1061,7 +1086,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         a.wmi[w0 + tid] = mi;
         a.wflags[w0 + tid] = fl;
     }
-    __syncthreads();
+    block_sync();
     if (tid < (int)nwin) {
         const uint32_t w = w0 + tid, q = L.query[tid];
         const QDesc qd = a.qd[q];
@@ -1079,7 +1104,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 // main: persistent loop over items
 // --------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 5 : 1))) void main_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
@@ -1091,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
     if (a.persistent) {
         if (tid == 0)
             s_item = atomicAdd(a.counter, 1u);
-        __syncthreads();
+        block_sync();
     }
     for (uint32_t iter = 0;; ++iter) {
         uint32_t it;
@@ -1121,12 +1146,12 @@ __global__ __launch_bounds__(kBlock) void main_kernel(LaunchArgs a)
             split_item<K>(a, itm.win, (int)itm.info, buf, s_part, s_red);
             __builtin_amdgcn_s_setprio(0);
         }
-        __syncthreads();
+        block_sync();
         // take the next item only now: a workgroup still busy must not hold
         // one (items are largest first); other workgroups keep the CU busy
         if (a.persistent && tid == 0)
             s_item = atomicAdd(a.counter, 1u);
-        __syncthreads();
+        block_sync();
     }
 }
 

@@ -173,7 +173,9 @@ def test_config2_replay_bit_identical(store, cfg2):
         torch.ones(1000, device="cuda").sum().item()  # eager work between replays
         b.replay()
         again = b.read()
-        assert np.array_equal(first.view(np.uint8), again.view(np.uint8)), r
+        rows = np.nonzero(np.any(first.view(np.uint64).reshape(len(first), -1)
+                                 != again.view(np.uint64).reshape(len(first), -1), axis=1))[0]
+        assert len(rows) == 0, (r, len(rows), np.unique(q["len"][rows], return_counts=True))
     b.destroy()
 
 
