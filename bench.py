@@ -15,7 +15,10 @@ Also reported: the same steps as HIP-graph launches, the plain form (one
 prep + one main launch per window), end-to-end query latency (fresh submit ->
 results on host), the roofline of the main kernel, the serving loop on 1024
 resident series of 2^20 points under a Poisson request stream (p50/p99
-latency, throughput) and the CPU oracle on the host's cores.
+latency, throughput), the all-pairs noise search (64 x 32,768, 2016 pairs,
+8,195,040 noise triples) and the large-search hot path on one pair of 2^24
+points (every top-down layer, 4,161,487 windows), and the CPU oracle on the
+host's cores.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -189,6 +192,45 @@ def serve_bench(args, torch, synth, wmi) -> dict:
     return out
 
 
+def chunked_bench(wmi, torch, w, steps: int) -> dict:
+    """A workload too large for one batch: consecutive batches of the whole
+    query set (submit_many), series resident; one pass = a direct replay of
+    every batch, enqueued back to back (each batch on its own stream)."""
+    st = wmi.Store(0, budget_bytes=4 << 30)
+    ids = [st.add_series(s) for s in w.series]
+    assert ids == list(range(len(w.series)))
+    t0 = time.perf_counter()
+    batches = st.submit_many(w.queries, k=w.k, tau=w.tau)
+    for b in batches:
+        b.wait()
+    t_submit = time.perf_counter() - t0
+    for b in batches:  # warm-up pass
+        b.replay(direct=True)
+    for b in batches:
+        b.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for b in batches:
+            b.replay(direct=True)
+    for b in batches:
+        b.wait()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    main_ms = float(sum(b.timing()["main_ms"] for b in batches))
+    for b in batches:
+        b.destroy()
+    st.close()
+    pairs = w.ordered_pairs
+    return {"workload": w.name, "note": w.note, "queries": int(len(w.queries)), "windows": int(w.n_windows),
+            "ordered_pairs": int(pairs), "batches": len(batches), "passes": steps, "ms_per_pass": dt * 1e3,
+            "windows_per_s": w.n_windows / dt, "pairs_per_s": pairs / dt,
+            "distance_ops_frac_valu_peak": pairs * OPS_PER_PAIR / dt / 1e12 / VALU_PEAK_TOPS,
+            "main_kernel_ms_sum": main_ms,
+            "main_kernel_frac_valu_peak": pairs * OPS_PER_PAIR / (main_ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+            "first_submit_s": t_submit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +244,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-burst", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the all-pairs and large-search workloads")
+    ap.add_argument("--large-passes", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -334,6 +379,13 @@ def main():
     }
     if not args.no_serve:
         out["serving"] = serve_bench(args, torch, synth, wmi)
+    if not args.no_large:
+        log("all-pairs noise search (64 x 32768, 2016 pairs, triples) ...")
+        out["all_pairs_noise"] = chunked_bench(wmi, torch, synth.config3(), args.large_passes)
+        log(f"all-pairs: {out['all_pairs_noise']}")
+        log("large-search proxy (one pair of 2^24, 7 dense layers) ...")
+        out["large_search_proxy"] = chunked_bench(wmi, torch, synth.config5_proxy(), args.large_passes)
+        log(f"large-search proxy: {out['large_search_proxy']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -18,7 +18,9 @@ Workloads (stand-ins for the paper's NYC / energy data, which are not public):
   in the factors, half with quadratic / sine links; all 2016 pairs, w=256,
   stride 8, every position a noise triple (248-sample overlap + 8 new samples).
 * ``config4``  serving: cfg2-style pairs, a Poisson stream of queries.
-* ``config5``  IoT-like seasonal + AR(1) series with injected bursts.
+* ``config5``  IoT-like seasonal + AR(1) series with injected bursts;
+  ``config5_proxy``: one pair, every top-down layer (w = 4096 .. 64,
+  stride w/8) evaluated densely.
 
 The relation types of the paper's synthetic-data table (Section 8.3.1) are
 available through ``relation`` for qualitative tests.
@@ -280,6 +282,20 @@ def config5_series(seed: int = 5, n_series: int = 8, n: int = 1 << 24):
             v[st:st + L] = seg + 0.1 * r.standard_normal(L)
         out.append(quantize(v))
     return out
+
+
+CFG5_LAYERS = (4096, 2048, 1024, 512, 256, 128, 64)
+
+
+def config5_proxy(seed: int = 5, n: int = 1 << 24) -> Workload:
+    """The hot path of the large search on one series pair: every layer of a
+    top-down sweep evaluated densely (w = 4096, 2048, ..., 64, stride w/8)
+    over the whole pair.  The pair is the config5 recipe with two series
+    (each one's bursts copied from the other)."""
+    series = config5_series(seed, n_series=2, n=n)
+    q = np.concatenate([make_queries(0, 1, sliding(n, w, w // 8), w) for w in CFG5_LAYERS])
+    return Workload(f"cfg5_td_dense_pair_n{n}_w64-4096_s8th", series, q, k=4,
+                    note="IoT-like pair, 7 halving layers, stride w/8, k=4")
 
 
 def _ar1(innov: np.ndarray, phi: float) -> np.ndarray:

@@ -300,6 +300,21 @@ class Store:
                                 _stream_handle(stream), ctypes.byref(h)))
         return Batch(self, h.value, len(q))
 
+    def submit_many(self, queries, max_queries: int = 1 << 18, max_points: int = 1 << 26, **kw) -> list:
+        """Submit a large query set as consecutive batches, each of at most
+        max_queries queries and (once it holds one) max_points window points;
+        a query and its windows stay together."""
+        q = as_queries(queries)
+        pts = q["len"].astype(np.int64) + np.where(q["ext_side"] != 0, q["len"] + 2 * q["ext_len"].astype(np.int64), 0)
+        cum = np.concatenate([[0], np.cumsum(pts)])
+        out, i = [], 0
+        while i < len(q):
+            j = int(np.searchsorted(cum, cum[i] + max_points, side="right")) - 1
+            j = min(max(j, i + 1), i + max_queries, len(q))
+            out.append(self.submit(q[i:j], **kw))
+            i = j
+        return out
+
     def evaluate(self, queries, **kw) -> np.ndarray:
         b = self.submit(queries, **kw)
         try:

@@ -265,3 +265,40 @@ def test_errors(wmi, store):
             store.remove_series(extra)  # finished: no longer pinned
         with pytest.raises(W.WmiError):
             srv.read(t)  # ticket forgotten after read
+
+
+def test_two_hundred_requests_alone_mix_oracle(wmi, store, series, orc):
+    """The serving workload's request shape (random pair, w log-uniform in
+    [32, 2048], stride w/4) on resident series: 200 requests, each alone on an
+    idle server and all of them in flight together, bit-identical; every
+    window equal to the batch entry point's; one window of each against the
+    oracle."""
+    r = np.random.default_rng(404)
+    reqs = []
+    for _ in range(200):
+        w = int(np.rint(np.exp(r.uniform(np.log(32), np.log(2048)))))
+        a = int(r.integers(0, N_SERIES))
+        b = int((a + r.integers(1, N_SERIES)) % N_SERIES)
+        start = int(r.integers(0, N // 4))
+        reqs.append((a, b, start, N, w, max(w // 4, 1)))
+    with wmi.Server(store, k=4) as srv:
+        alone = [run_requests(srv, [q])[0] for q in reqs]
+    with wmi.Server(store, k=4, max_launch_windows=16384) as srv:
+        mixed = run_requests(srv, reqs)
+        st = srv.stats()
+    log(f"200-request mix: {st}")
+    assert st["launches"] < len(reqs)
+    # the batch entry point on every window of every request, in one batch
+    qs = [synth.make_queries(q[0], q[1], windows_of(q), q[4]) for q in reqs]
+    ref = store.evaluate(np.concatenate(qs), k=4)
+    off = 0
+    for i, (req, (g1, _), (g2, _)) in enumerate(zip(reqs, alone, mixed)):
+        assert np.array_equal(g1["mi"].view(np.uint64), g2["mi"].view(np.uint64)), req
+        assert np.array_equal(g1["flags"], g2["flags"]), req
+        n = len(g1)
+        same(g1, ref["mi_base"][off:off + n], ref["flags"][off:off + n])
+        off += n
+        j = int(r.integers(0, n))
+        s0 = int(windows_of(req)[j])
+        mi = orc.window_mi(series[req[0]][s0:s0 + req[4]], series[req[1]][s0:s0 + req[4]], k=4)
+        assert abs(g1["mi"][j] - mi) <= TOL, (req, j, g1["mi"][j], mi)
