@@ -107,28 +107,67 @@ __device__ __forceinline__ uint32_t ceil_log2(uint32_t m)
     return b;
 }
 
-// #{S[0..n) < v} and #{S[0..n) <= v} for ascending S; the loop trip count
-// depends on n only, so lanes stay converged.
-__device__ __forceinline__ int count_lt(const int32_t *S, int n, int32_t v)
+// #{S[0..n) < v} for NX thresholds in sx and NX in sy (ascending arrays of n
+// entries), the searches interleaved step by step so that their LDS reads
+// overlap.  The trip count depends on n only.
+template <int NX>
+__device__ __forceinline__ void count_lt_xy(const int32_t *sx, const int32_t *sy, int n, const int32_t (&vx)[NX],
+                                            const int32_t (&vy)[NX], int (&cx)[NX], int (&cy)[NX])
 {
-    int base = 0;
+    int bx[NX], by[NX];
+#pragma unroll
+    for (int t = 0; t < NX; ++t)
+        bx[t] = by[t] = 0;
     while (n > 1) {
-        int half = n >> 1;
-        base = (S[base + half] < v) ? base + half : base;
+        const int half = n >> 1;
+        int32_t ex[NX], ey[NX];
+#pragma unroll
+        for (int t = 0; t < NX; ++t) {
+            ex[t] = sx[bx[t] + half];
+            ey[t] = sy[by[t] + half];
+        }
+#pragma unroll
+        for (int t = 0; t < NX; ++t) {
+            bx[t] = ex[t] < vx[t] ? bx[t] + half : bx[t];
+            by[t] = ey[t] < vy[t] ? by[t] + half : by[t];
+        }
         n -= half;
     }
-    return base + (S[base] < v ? 1 : 0);
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+        cx[t] = bx[t] + (sx[bx[t]] < vx[t] ? 1 : 0);
+        cy[t] = by[t] + (sy[by[t]] < vy[t] ? 1 : 0);
+    }
 }
 
-__device__ __forceinline__ int count_le(const int32_t *S, int n, int32_t v)
+// Search thresholds of one point for count_lt_xy (two per dimension), from
+// its grid integers and radii.  Estimator 0 counts |d| <= e:
+// #{< v + e + 1} - #{< v - e};  estimator 1 counts |d| < e:
+// #{< v + e} - #{< v - e + 1}.
+__device__ __forceinline__ void count_bounds(uint32_t est, int32_t xi, int32_t yi, int32_t ex, int32_t ey,
+                                             int32_t *vx, int32_t *vy)
 {
-    int base = 0;
-    while (n > 1) {
-        int half = n >> 1;
-        base = (S[base + half] <= v) ? base + half : base;
-        n -= half;
+    const int32_t o = est == 0 ? 1 : 0;
+    vx[0] = xi + ex + o;
+    vx[1] = xi - ex + 1 - o;
+    vy[0] = yi + ey + o;
+    vy[1] = yi - ey + 1 - o;
+}
+
+// Digamma terms of one point from its four counts (the point itself, inside
+// every interval, is removed); estimator 1 counts nothing at zero radius and
+// uses psi(n + 1).
+__device__ __forceinline__ long long point_terms(const LaunchArgs &a, int hx, int lx, int hy, int ly, int32_t ex,
+                                                 int &cx, int &cy)
+{
+    if (a.estimator == 0) {
+        cx = hx - lx - 1;
+        cy = hy - ly - 1;
+        return a.psi_fix[cx] + a.psi_fix[cy];
     }
-    return base + (S[base] <= v ? 1 : 0);
+    cx = ex > 0 ? hx - lx - 1 : 0;
+    cy = ex > 0 ? hy - ly - 1 : 0;
+    return a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
 }
 
 // --------------------------------------------------------------------------
@@ -159,16 +198,26 @@ __global__ void clear_kernel(LaunchArgs a)
 // NA == 2), as segments of P entries each (P a power of two dividing total,
 // total <= 2 * R * kBlock).  Each stage pairs entry lo with lo + stride; a
 // thread takes pairs tid + r * kBlock and loads all of them before any
-// compare, so their LDS latencies overlap.  A workgroup barrier precedes
-// every stage.  Called by the whole workgroup; ends with a barrier.
+// compare, so their LDS latencies overlap.  The 64 pairs a wave takes for one
+// r cover one block of 128 consecutive entries whenever stride <= 64: two
+// such stages in a row touch only the wave's own blocks, and between them
+// the wave only waits for its own LDS stores to complete.  Every other stage
+// starts with a workgroup barrier.  Called by the whole workgroup; ends with
+// a barrier.
 template <int R, int NA>
 __device__ void bitonic_lds(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t npairs = total >> 1;
+    bool prev_local = false;
     for (uint32_t size = 2; size <= P; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            block_sync();
+            const bool local = stride <= 64u;
+            if (local && prev_local)
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            else
+                block_sync();
+            prev_local = local;
             int32_t va[R][2], vb[R][2];
             uint32_t lo[R];
 #pragma unroll
@@ -330,29 +379,6 @@ __device__ __forceinline__ double window_estimate(const LaunchArgs &a, int m, lo
     if (a.estimator == 0)
         return (a.psi_d[K] - 1.0 / (double)K + a.psi_d[m]) - Sd / (double)m;
     return (a.psi_d[K] + a.psi_d[m]) - Sd / (double)m;
-}
-
-// Marginal counts of a point from the sorted marginals of its window, and the
-// fixed-point digamma terms (Eq. 2; estimator 1 uses psi(n + 1)).
-__device__ __forceinline__ long long count_terms(const LaunchArgs &a, const int32_t *sx, const int32_t *sy,
-                                                 int m, int32_t xi, int32_t yi, int32_t ex, int32_t ey,
-                                                 int &cx, int &cy)
-{
-    if (a.estimator == 0) {
-        cx = count_le(sx, m, xi + ex) - count_lt(sx, m, xi - ex) - 1;
-        cy = count_le(sy, m, yi + ey) - count_lt(sy, m, yi - ey) - 1;
-        return a.psi_fix[cx] + a.psi_fix[cy];
-    }
-    // strict counts inside the joint radius; a zero radius counts nothing
-    // (the open interval is empty), otherwise the point itself is inside
-    if (ex > 0) {
-        cx = count_lt(sx, m, xi + ex) - count_le(sx, m, xi - ex) - 1;
-        cy = count_lt(sy, m, yi + ey) - count_le(sy, m, yi - ey) - 1;
-    } else {
-        cx = 0;
-        cy = 0;
-    }
-    return a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
 }
 
 // Radii of one query (grid units) from the keys of its k neighbours; the
@@ -673,7 +699,10 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
     const int32_t *src = a.sorted + 2ull * d.sorted_off;
     int32_t *sx = reinterpret_cast<int32_t *>(buf);
     int32_t *sy = sx + kChunk;
-    const bool strict = a.estimator != 0;
+    int32_t vx[2 * Q], vy[2 * Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        count_bounds(a.estimator, xi[q], yi[q], (int32_t)rx[q], (int32_t)ry[q], vx + 2 * q, vy + 2 * q);
     for (int c0 = 0; c0 < m; c0 += kChunk) {
         const int cn = min(kChunk, m - c0);
         block_sync();
@@ -682,21 +711,14 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
             sy[i] = src[m + c0 + i];
         }
         block_sync();
+        int cxs[2 * Q], cys[2 * Q];
+        count_lt_xy<2 * Q>(sx, sy, cn, vx, vy, cxs, cys);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int32_t ex = (int32_t)rx[q], ey = (int32_t)ry[q];
-            // estimator 0: #{<= x+e} - #{< x-e};  estimator 1: #{< x+e} - #{<= x-e}
-            if (strict) {
-                hx[q] += count_lt(sx, cn, xi[q] + ex);
-                lx[q] += count_le(sx, cn, xi[q] - ex);
-                hy[q] += count_lt(sy, cn, yi[q] + ey);
-                ly[q] += count_le(sy, cn, yi[q] - ey);
-            } else {
-                hx[q] += count_le(sx, cn, xi[q] + ex);
-                lx[q] += count_lt(sx, cn, xi[q] - ex);
-                hy[q] += count_le(sy, cn, yi[q] + ey);
-                ly[q] += count_lt(sy, cn, yi[q] - ey);
-            }
+            hx[q] += cxs[2 * q];
+            lx[q] += cxs[2 * q + 1];
+            hy[q] += cys[2 * q];
+            ly[q] += cys[2 * q + 1];
         }
     }
     long long part = 0;
@@ -706,16 +728,7 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
         if (i >= m)
             continue;
         int cx, cy;
-        if (!strict) {
-            cx = hx[q] - lx[q] - 1;
-            cy = hy[q] - ly[q] - 1;
-            part += a.psi_fix[cx] + a.psi_fix[cy];
-        } else {
-            // a zero joint radius counts nothing; otherwise the point itself is inside
-            cx = rx[q] > 0 ? hx[q] - lx[q] - 1 : 0;
-            cy = rx[q] > 0 ? hy[q] - ly[q] - 1 : 0;
-            part += a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
-        }
+        part += point_terms(a, hx[q], lx[q], hy[q], ly[q], (int32_t)rx[q], cx, cy);
         if (a.dbg_nx) {
             a.dbg_nx[i] = (uint32_t)cx;
             a.dbg_ny[i] = (uint32_t)cy;
@@ -1048,25 +1061,32 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     // ---- sort every window's marginals (segments of P, padded with INT32_MAX)
     bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, nwin << lp, P);
 
-    // ---- counts and digamma terms
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (!act[q])
-            continue;
-        const uint32_t w = W[q];
+    // ---- counts and digamma terms: both slots of a thread lie in one window,
+    // so their eight searches run interleaved over the same sorted marginals
+    if (act[0] && (int)L.m[W[0]] > K) {
+        const uint32_t w = W[0];
         const int m = (int)L.m[w];
-        if (m <= K)
-            continue;
-        int cx, cy;
-        long long t = count_terms(a, srt_x + (w << lp), srt_y + (w << lp), m, X[q], Y[q], (int32_t)RX[q],
-                                  (int32_t)RY[q], cx, cy);
-        atomicAdd(&L.acc[w], (unsigned long long)t);
-        if (a.dbg_nx) {
-            a.dbg_nx[I[q]] = (uint32_t)cx;
-            a.dbg_ny[I[q]] = (uint32_t)cy;
-            a.dbg_ex[I[q]] = (float)RX[q] * (1.0f / 4096.0f);
-            a.dbg_ey[I[q]] = (float)RY[q] * (1.0f / 4096.0f);
+        int32_t vx[4], vy[4];
+        int cxs[4], cys[4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            count_bounds(a.estimator, X[q], Y[q], (int32_t)RX[q], (int32_t)RY[q], vx + 2 * q, vy + 2 * q);
+        count_lt_xy<4>(srt_x + (w << lp), srt_y + (w << lp), m, vx, vy, cxs, cys);
+        long long t = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (!act[q])
+                continue;
+            int cx, cy;
+            t += point_terms(a, cxs[2 * q], cxs[2 * q + 1], cys[2 * q], cys[2 * q + 1], (int32_t)RX[q], cx, cy);
+            if (a.dbg_nx) {
+                a.dbg_nx[I[q]] = (uint32_t)cx;
+                a.dbg_ny[I[q]] = (uint32_t)cy;
+                a.dbg_ex[I[q]] = (float)RX[q] * (1.0f / 4096.0f);
+                a.dbg_ey[I[q]] = (float)RY[q] * (1.0f / 4096.0f);
+            }
         }
+        atomicAdd(&L.acc[w], (unsigned long long)t);
     }
     block_sync();
 
