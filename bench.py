@@ -231,6 +231,37 @@ def chunked_bench(wmi, torch, w, steps: int) -> dict:
             "first_submit_s": t_submit}
 
 
+def td_bench(wmi, torch, w) -> dict:
+    """Top-down search (library driver) over the large-search pair with the
+    paper's thresholds (normalised sigma = 0.2, tau = sigma / 4), windows 4096
+    down to 64, step w/8; without pruning and with pruning after p = 2
+    consecutive noise detections, the latter graded by overlap accuracy."""
+    from paper_2204_09131_amd.search import overlap_accuracy
+    st = wmi.Store(0, budget_bytes=4 << 30)
+    a, b = st.add_series(w.series[0]), st.add_series(w.series[1])
+    n = len(w.series[0])
+    kw = dict(s_max=4096, s_min=64, sigma=0.2, tau=0.05, step_div=8, normalize=True, k=4)
+    out = {"workload": f"top-down search, {w.name.split('_td_')[0]} pair of {n} points", "params": kw}
+    runs = {}
+    for p in (0, 2):
+        st.td_search(a, b, 0, min(n, 1 << 20), p=p, **kw)  # warm-up on a prefix
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        found, stats = st.td_search(a, b, 0, n, p=p, **kw)
+        dt = time.perf_counter() - t0
+        runs[p] = found
+        out[f"p{p}"] = {"seconds": dt, "windows_found": int(len(found)),
+                        "covered_points": int(found["len"].astype(np.int64).sum()),
+                        "pairs_per_s": stats["ordered_pairs"] / dt, **stats}
+        log(f"td p={p}: {out[f'p{p}']}")
+    ref = [(int(r["start"]), int(r["len"])) for r in runs[0]]
+    cand = [(int(r["start"]), int(r["len"])) for r in runs[2]]
+    out["pruning_overlap_accuracy"] = overlap_accuracy(ref, cand)
+    out["pruning_speedup"] = out["p0"]["seconds"] / out["p2"]["seconds"]
+    st.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,8 +415,11 @@ def main():
         out["all_pairs_noise"] = chunked_bench(wmi, torch, synth.config3(), args.large_passes)
         log(f"all-pairs: {out['all_pairs_noise']}")
         log("large-search proxy (one pair of 2^24, 7 dense layers) ...")
-        out["large_search_proxy"] = chunked_bench(wmi, torch, synth.config5_proxy(), args.large_passes)
+        w5 = synth.config5_proxy()
+        out["large_search_proxy"] = chunked_bench(wmi, torch, w5, args.large_passes)
         log(f"large-search proxy: {out['large_search_proxy']}")
+        log("top-down search over the large-search pair ...")
+        out["top_down_search"] = td_bench(wmi, torch, w5)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -324,6 +324,72 @@ double wmi_server_clock_us(wmi_server *server);
 /* Finish every pending request, stop the scheduler and free the server. */
 int wmi_server_destroy(wmi_server *server);
 
+/* ==========================================================================
+ * Search drivers: native host code that walks one of the paper's search
+ * rules over a series pair and evaluates the candidate windows in batches
+ * through the path above.  A driver's result is exactly that of the rule
+ * applied window by window; the batching only decides which windows are
+ * evaluated together on the device.
+ * ========================================================================== */
+
+typedef struct {                 /* 24 bytes */
+    uint64_t start;              /* window [start, start + len) of the pair      */
+    uint32_t len;
+    uint32_t layer;              /* top-down: layer (0 = s_max)                   */
+    double mi;                   /* I_w in nats                                   */
+} wmi_window;
+
+typedef struct {
+    uint64_t layers;             /* layers searched                               */
+    uint64_t windows_visited;    /* windows the sequential rule examined          */
+    uint64_t windows_evaluated;  /* windows evaluated on the device (a noise
+                                    triple counts 3)                              */
+    uint64_t ordered_pairs;      /* sum of m (m - 1) over evaluated windows       */
+    uint64_t noise_detections;   /* shifted windows whose new part was noise      */
+    uint64_t noise_skips;        /* shifts cancelled after p detections in a row  */
+    uint64_t batches;            /* batches submitted                             */
+    double wall_ms;              /* whole call                                    */
+} wmi_search_stats;
+
+/*
+ * Top-down search (Algorithm 1, Section 5.1) with noise-based pruning
+ * (Section 6.2).  Layer 0 slides windows of s_max points over [begin, end);
+ * each later layer halves the window size, down to s_min, and slides over
+ * the uncorrelated partitions the layer above left: the stretches of its
+ * partitions not covered by a correlated window.  Inside a partition a window
+ * w with I_w >= sigma is correlated and reported, and the next window starts
+ * where w ends; otherwise the next window is w shifted by the layer's step
+ * delta = max(1, s_w / step_div).  With pruning (p > 0) a shifted window is
+ * split into its overlap with the previous window and its delta new points;
+ * when Definition 6.2 flags the new part as noise in p consecutive shifted
+ * windows, the shift is cancelled and the next window starts where the last
+ * one ends.
+ *   s_max, s_min : 2 <= s_min <= s_max <= WMI_MAX_WINDOW.
+ *   step_div     : 0 means 8.
+ *   normalize    : 1 compares I_w >= sigma * ln|w| and I(w_d) < tau * ln|w_d|
+ *                  (normalised MI with the entropy of |w| distinct samples).
+ * Output: the correlated windows in ascending start order (non-overlapping),
+ * written to host_out (capacity entries; (end - begin) / s_min + 1 always
+ * suffice); *n_out receives their number.  WMI_EINVAL for bad ids, ranges or
+ * parameters, or a capacity below the number found (nothing written).
+ * stats may be NULL.  Synchronous; uses the store's stream.
+ */
+typedef struct {
+    uint32_t s_max, s_min;
+    uint32_t step_div;
+    uint32_t p;
+    double sigma;
+    double tau;
+    uint32_t normalize;
+    uint32_t k;
+    uint32_t estimator;
+    uint32_t flags;              /* 0 */
+} wmi_td_params;
+
+int wmi_td_search(wmi_store *store, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
+                  const wmi_td_params *params, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
+                  wmi_search_stats *stats);
+
 /* Copy the library's double-precision digamma table psi(1..n) (n <= 8192)
  * to host_out (for checks against an independent construction). */
 int wmi_psi_table(uint32_t n, double *host_out);

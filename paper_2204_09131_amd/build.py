@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwmi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["wmi_kernels.hip", "wmi_runtime.cpp", "psi_table.cpp", "wmi_server.cpp"]
+SOURCES = ["wmi_kernels.hip", "wmi_runtime.cpp", "psi_table.cpp", "wmi_server.cpp", "wmi_search.cpp"]
 ARCH = os.environ.get("WMI_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

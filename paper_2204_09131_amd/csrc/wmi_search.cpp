@@ -1,0 +1,241 @@
+// wmi_search.cpp -- search drivers over the batch path (include/wmi.h).
+//
+// Top-down search (Algorithm 1, Section 5.1) with noise pruning (Section
+// 6.2).  The rule is sequential inside a partition: whether the next window
+// is shifted by the step or starts after the current one depends on the
+// current window's estimate.  Every window the rule can reach still lies on
+// the partition's grid of starts ps, ps + delta, ... whenever delta divides
+// the window size (a jump of s_w is a whole number of steps), so a layer is
+// evaluated speculatively: all grid windows of all partitions in a few large
+// batches (as noise triples when pruning is on), then the rule walks each
+// partition on the host over those estimates.  When delta does not divide
+// s_w the walk meets windows off the grid; those are evaluated in follow-up
+// batches and the walk resumes.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "wmi.h"
+#include "wmi_store.h"
+
+using namespace wmi;
+
+namespace {
+
+constexpr uint64_t kChunkQueries = 1ull << 18;
+constexpr uint64_t kChunkPoints = 1ull << 26;
+
+struct Eval {
+    double mi = 0.0;   // I(w)
+    bool noise = false;
+};
+
+// Evaluate windows of s_w points at the given starts (as noise triples with a
+// delta-point right extension when triple is set) in chunked batches.
+int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> &starts, uint32_t s_w,
+             uint32_t delta, bool triple, const wmi_params &prm, std::vector<Eval> &out, wmi_search_stats &stats)
+{
+    out.assign(starts.size(), Eval());
+    const uint64_t per_q = triple ? 2ull * s_w : s_w;
+    const uint64_t chunk = std::max<uint64_t>(1, std::min(kChunkQueries, kChunkPoints / per_q));
+    std::vector<wmi_query> q;
+    std::vector<wmi_result> r;
+    for (uint64_t i0 = 0; i0 < starts.size(); i0 += chunk) {
+        const uint64_t n = std::min<uint64_t>(chunk, starts.size() - i0);
+        q.assign(n, wmi_query());
+        for (uint64_t i = 0; i < n; ++i) {
+            wmi_query &x = q[i];
+            x.a = a;
+            x.b = b;
+            x.start = starts[i0 + i];
+            x.len = triple ? s_w - delta : s_w;
+            x.ext_len = triple ? delta : 0;
+            x.ext_side = triple ? 1 : 0;
+            x.reserved = 0;
+        }
+        wmi_batch *bt = nullptr;
+        if (int rc = wmi_submit(st, q.data(), n, &prm, nullptr, &bt))
+            return rc;
+        r.assign(n, wmi_result());
+        int rc = wmi_read(bt, r.data());
+        (void)wmi_batch_destroy(bt);
+        if (rc)
+            return rc;
+        for (uint64_t i = 0; i < n; ++i) {
+            out[i0 + i].mi = triple ? r[i].mi_union : r[i].mi_base;
+            out[i0 + i].noise = (r[i].flags & WMI_F_NOISE) != 0;
+        }
+        stats.batches++;
+        const uint64_t m = s_w, mo = s_w - delta, md = delta;
+        stats.windows_evaluated += triple ? 3 * n : n;
+        stats.ordered_pairs += n * (triple ? m * (m - 1) + mo * (mo - 1) + md * (md - 1) : m * (m - 1));
+    }
+    return WMI_OK;
+}
+
+struct Walk {
+    uint64_t ps, pe;     // partition [ps, pe)
+    uint64_t w;          // next window start
+    uint32_t run = 0;    // consecutive noise detections
+    bool shifted = false;
+    bool done = false;
+    std::vector<std::pair<uint64_t, uint64_t>> corr;  // correlated windows found
+};
+
+}  // namespace
+
+extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
+                             const wmi_td_params *p, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
+                             wmi_search_stats *stats_out)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!st || !p || !n_out)
+        return fail(WMI_EINVAL, "wmi_td_search: null argument");
+    *n_out = 0;
+    if (p->s_min < 2 || p->s_min > p->s_max || p->s_max > (uint32_t)WMI_MAX_WINDOW || p->flags)
+        return fail(WMI_EINVAL, "wmi_td_search: need 2 <= s_min <= s_max <= %d and flags 0", WMI_MAX_WINDOW);
+    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 1)
+        return fail(WMI_EINVAL, "wmi_td_search: bad k, estimator or normalize");
+    uint64_t na = 0, nb = 0;
+    if (int rc = wmi_series_length(st, a, &na))
+        return rc;
+    if (int rc = wmi_series_length(st, b, &nb))
+        return rc;
+    if (begin > end || end > std::min(na, nb))
+        return fail(WMI_EINVAL, "wmi_td_search: range [%llu, %llu) outside the series", (unsigned long long)begin,
+                    (unsigned long long)end);
+    const uint32_t div = p->step_div ? p->step_div : 8u;
+    wmi_params prm{};
+    prm.k = p->k;
+    prm.estimator = p->estimator;
+    prm.tau = p->tau;
+    prm.tau_normalize = p->normalize;
+    prm.flags = 0;
+
+    wmi_search_stats stats{};
+    std::vector<wmi_window> found;
+    std::vector<std::pair<uint64_t, uint64_t>> parts;
+    if (end - begin >= p->s_min)
+        parts.push_back({begin, end});
+    uint32_t layer = 0;
+    for (uint32_t s_w = p->s_max; s_w >= p->s_min; s_w /= 2, ++layer) {
+        if (parts.empty())
+            break;
+        stats.layers++;
+        const uint32_t delta = std::max(1u, s_w / div);
+        const bool triple = p->p > 0 && delta < s_w;
+        const double thr = p->normalize ? p->sigma * std::log((double)s_w) : p->sigma;
+        // speculative pass: every grid window of every partition
+        std::vector<Walk> walks;
+        std::vector<uint64_t> starts;
+        std::vector<uint64_t> grid0;  // first grid index of each partition
+        for (const auto &pr : parts) {
+            Walk wk;
+            wk.ps = pr.first;
+            wk.pe = pr.second;
+            wk.w = pr.first;
+            grid0.push_back(starts.size());
+            for (uint64_t s = pr.first; s + s_w <= pr.second; s += delta)
+                starts.push_back(s);
+            walks.push_back(std::move(wk));
+        }
+        std::vector<Eval> ev;
+        if (int rc = evaluate(st, a, b, starts, s_w, delta, triple, prm, ev, stats))
+            return rc;
+        std::map<uint64_t, Eval> extra;  // off-grid windows evaluated on demand
+        bool pending = true;
+        while (pending) {
+            pending = false;
+            std::vector<uint64_t> need;
+            for (size_t pi = 0; pi < walks.size(); ++pi) {
+                Walk &wk = walks[pi];
+                while (!wk.done) {
+                    if (wk.w + s_w > wk.pe) {
+                        wk.done = true;
+                        break;
+                    }
+                    const Eval *e = nullptr;
+                    const uint64_t off = wk.w - wk.ps;
+                    if (off % delta == 0) {
+                        e = &ev[grid0[pi] + off / delta];
+                    } else {
+                        auto it = extra.find(wk.w);
+                        if (it == extra.end()) {
+                            need.push_back(wk.w);
+                            break;
+                        }
+                        e = &it->second;
+                    }
+                    stats.windows_visited++;
+                    if (e->mi >= thr) {
+                        found.push_back(wmi_window{wk.w, s_w, layer, e->mi});
+                        wk.corr.push_back({wk.w, wk.w + s_w});
+                        wk.w += s_w;
+                        wk.run = 0;
+                        wk.shifted = false;
+                        continue;
+                    }
+                    if (triple && wk.shifted && e->noise) {
+                        stats.noise_detections++;
+                        wk.run++;
+                    } else {
+                        wk.run = 0;
+                    }
+                    if (triple && wk.run >= p->p) {
+                        stats.noise_skips++;
+                        wk.w += s_w;
+                        wk.run = 0;
+                        wk.shifted = false;
+                    } else {
+                        wk.w += delta;
+                        wk.shifted = true;
+                    }
+                }
+            }
+            if (!need.empty()) {
+                std::sort(need.begin(), need.end());
+                need.erase(std::unique(need.begin(), need.end()), need.end());
+                std::vector<Eval> ex;
+                if (int rc = evaluate(st, a, b, need, s_w, delta, triple, prm, ex, stats))
+                    return rc;
+                for (size_t i = 0; i < need.size(); ++i)
+                    extra[need[i]] = ex[i];
+                pending = true;
+            }
+        }
+        // uncorrelated partitions for the lower layers: each partition minus
+        // its correlated windows (stretches shorter than s_min can hold no
+        // window of any layer)
+        std::vector<std::pair<uint64_t, uint64_t>> np;
+        for (const Walk &wk : walks) {
+            uint64_t at = wk.ps;
+            for (const auto &c : wk.corr) {
+                if (c.first - at >= p->s_min)
+                    np.push_back({at, c.first});
+                at = c.second;
+            }
+            if (wk.pe - at >= p->s_min)
+                np.push_back({at, wk.pe});
+        }
+        parts.swap(np);
+        if (s_w == 1)
+            break;
+    }
+    std::sort(found.begin(), found.end(),
+              [](const wmi_window &x, const wmi_window &y) { return x.start < y.start; });
+    *n_out = found.size();
+    if (found.size() > capacity)
+        return fail(WMI_EINVAL, "wmi_td_search: %llu windows found, room for %llu", (unsigned long long)found.size(),
+                    (unsigned long long)capacity);
+    if (!found.empty() && !host_out)
+        return fail(WMI_EINVAL, "wmi_td_search: null output");
+    if (!found.empty())
+        std::memcpy(host_out, found.data(), found.size() * sizeof(wmi_window));
+    stats.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats_out)
+        *stats_out = stats;
+    return WMI_OK;
+}

@@ -44,6 +44,7 @@ RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f
 REQUEST_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("end", "<u8"), ("w", "<u4"),
                           ("stride", "<u4")])
 WINDOW_RESULT_DTYPE = np.dtype([("mi", "<f8"), ("flags", "<u4"), ("pad", "<u4")])
+WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("mi", "<f8")])
 
 # the symbols include/wmi.h declares
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
@@ -51,7 +52,8 @@ EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destr
            "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
            "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
-           "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy")
+           "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
+           "wmi_td_search")
 REPLAY_DIRECT = 1
 
 
@@ -100,6 +102,20 @@ class _ServerStats(ctypes.Structure):
                 ("arena_peak_bytes", ctypes.c_uint64), ("queued_peak", ctypes.c_uint64)]
 
 
+class _TdParams(ctypes.Structure):
+    _fields_ = [("s_max", ctypes.c_uint32), ("s_min", ctypes.c_uint32), ("step_div", ctypes.c_uint32),
+                ("p", ctypes.c_uint32), ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
+                ("normalize", ctypes.c_uint32), ("k", ctypes.c_uint32), ("estimator", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class _SearchStats(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_uint64), ("windows_visited", ctypes.c_uint64),
+                ("windows_evaluated", ctypes.c_uint64), ("ordered_pairs", ctypes.c_uint64),
+                ("noise_detections", ctypes.c_uint64), ("noise_skips", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("wall_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -141,6 +157,7 @@ def lib():
         "wmi_server_stats_get": ([vp, P(_ServerStats)], ctypes.c_int),
         "wmi_server_clock_us": ([vp], ctypes.c_double),
         "wmi_server_destroy": ([vp], ctypes.c_int),
+        "wmi_td_search": ([vp, u32, u32, u64, u64, P(_TdParams), vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -321,6 +338,21 @@ class Store:
             return b.read()
         finally:
             b.destroy()
+
+    def td_search(self, a: int, b: int, begin: int, end: int, s_max: int, s_min: int, sigma: float,
+                  tau: float = 0.0, p: int = 0, step_div: int = 8, normalize: bool = False, k: int = 4,
+                  estimator: int = 0):
+        """Top-down search (wmi_td_search): correlated windows (WINDOW_DTYPE,
+        ascending start) and the search counters."""
+        prm = _TdParams(int(s_max), int(s_min), int(step_div), int(p), float(sigma), float(tau),
+                        1 if normalize else 0, int(k), int(estimator), 0)
+        cap = max(1, (int(end) - int(begin)) // max(int(s_min), 1) + 1)
+        out = np.zeros(cap, dtype=WINDOW_DTYPE)
+        n = ctypes.c_uint64()
+        st = _SearchStats()
+        _check(lib().wmi_td_search(self.h, int(a), int(b), int(begin), int(end), ctypes.byref(prm),
+                                   out.ctypes.data, cap, ctypes.byref(n), ctypes.byref(st)))
+        return out[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
 
     def debug_window(self, a: int, b: int, start: int, length: int, k: int = 4, estimator: int = 0) -> dict:
         q = np.zeros(1, dtype=QUERY_DTYPE)

@@ -1,0 +1,92 @@
+"""Pins of the sequential search rules in oracle/search.py, on constructed
+estimate functions whose outcome can be worked out by hand from Algorithm 1
+(Section 5.1) and the pruning rule of Section 6.2."""
+import math
+
+import pytest
+
+from oracle import search
+
+
+def test_everything_correlated_tiles_each_layer():
+    # sigma = -inf: every examined window is correlated.  Layer 0 tiles
+    # [0, 1000) with 256-point windows from 0; the 232-point tail goes down to
+    # 128, then its 104-point tail to 64; 40 points are left.
+    found = search.top_down(lambda t, m: 0.0, 0, 1000, 256, 64, -math.inf)
+    assert [(s, m, l) for s, m, l, _ in found] == [
+        (0, 256, 0), (256, 256, 0), (512, 256, 0), (768, 128, 1), (896, 64, 2)]
+
+
+def test_nothing_correlated_slides_every_layer_over_everything():
+    trace = []
+    found = search.top_down(lambda t, m: 0.0, 0, 1000, 256, 64, math.inf, trace=trace)
+    assert found == []
+    # steps 32, 16, 8: starts 0..744, 0..872, 0..936
+    assert len(trace) == (744 // 32 + 1) + (872 // 16 + 1) + (936 // 8 + 1) == 197
+    assert trace[:3] == [(0, 0), (0, 32), (0, 64)] and trace[-1] == (2, 936)
+
+
+def test_planted_block():
+    # I = 1 for windows inside [300, 700), else 0.  Layer 0 (256, step 32)
+    # finds [320, 576); layer 1 (128, step 16) fits nothing inside either
+    # remaining partition; layer 2 (64, step 8) finds [576, 640) in
+    # [576, 1000) and nothing in [0, 320).
+    def mi(t, m):
+        return 1.0 if (t >= 300 and t + m <= 700) else 0.0
+    found = search.top_down(mi, 0, 1000, 256, 64, 0.5)
+    assert [(s, m, l) for s, m, l, _ in found] == [(320, 256, 0), (576, 64, 2)]
+
+
+def test_noise_pruning_cancels_shifts_after_p_detections():
+    # Every shifted 64-point window is noise w.r.t. its overlap (I_o = 0.4 > 0,
+    # I_d = 0 < tau, I = 0.3 < I_o) and nothing is correlated.  With p = 2:
+    # 0 (not shifted) -> 8 (1st detection) -> 16 (2nd: skip) -> 80 -> 88 ->
+    # 96 (skip) -> 160, which no longer fits in [0, 200).
+    def mi(t, m):
+        return {64: 0.3, 56: 0.4, 8: 0.0}[m]
+    trace = []
+    found = search.top_down(mi, 0, 200, 64, 64, 0.5, tau=0.1, p=2, trace=trace)
+    assert found == []
+    assert [t for _, t in trace] == [0, 8, 16, 80, 88, 96]
+    # without pruning every step is taken
+    trace = []
+    search.top_down(mi, 0, 200, 64, 64, 0.5, tau=0.1, p=0, trace=trace)
+    assert [t for _, t in trace] == list(range(0, 137, 8))
+
+
+@pytest.mark.parametrize("case", ["nonpositive_base", "union_not_lower", "new_part_informative"])
+def test_noise_needs_all_three_conditions(case):
+    # Definition 6.2: I(w_o) > 0, I(w_d) < tau and I(w'') < I(w_o); break one
+    # condition and no shift is ever cancelled.
+    vals = {"nonpositive_base": {64: 0.3, 56: 0.0, 8: 0.0},
+            "union_not_lower": {64: 0.45, 56: 0.4, 8: 0.0},
+            "new_part_informative": {64: 0.3, 56: 0.4, 8: 0.2}}[case]
+    trace = []
+    search.top_down(lambda t, m: vals[m], 0, 200, 64, 64, 0.5, tau=0.1, p=1, trace=trace)
+    assert [t for _, t in trace] == list(range(0, 137, 8))
+
+
+def test_detections_must_be_consecutive():
+    # Noise only on shifted windows starting at multiples of 16: detections
+    # never come twice in a row, so p = 2 cancels nothing, while p = 1 jumps
+    # after the first detection (8 is not noise, 16 is).
+    def mi(t, m):
+        if m == 64:
+            return 0.3
+        if m == 56:
+            return 0.4
+        return 0.0 if (t - 56) % 16 == 0 else 0.2
+    trace = []
+    search.top_down(mi, 0, 200, 64, 64, 0.5, tau=0.1, p=2, trace=trace)
+    assert [t for _, t in trace] == list(range(0, 137, 8))
+    trace = []
+    search.top_down(mi, 0, 200, 64, 64, 0.5, tau=0.1, p=1, trace=trace)
+    assert [t for _, t in trace] == [0, 8, 16, 80, 88, 96]
+
+
+def test_normalized_thresholds():
+    # normalize: correlated iff I >= sigma ln|w|.  I = 0.45 ln 64 meets
+    # sigma = 0.45 exactly at 64 points and falls short at 128 (ln 128 > ln 64)
+    v = 0.45 * math.log(64)
+    found = search.top_down(lambda t, m: v, 0, 128, 128, 64, 0.45, normalize=True)
+    assert [(s, m) for s, m, _, _ in found] == [(0, 64), (64, 64)]
