@@ -262,6 +262,36 @@ def td_bench(wmi, torch, w) -> dict:
     return out
 
 
+def bu_bench(wmi, torch, w) -> dict:
+    """Bottom-up search (library driver, 1024 walkers over chunks of 16,384
+    points) over the large-search pair with the paper's thresholds, windows
+    64 to 4096, moving step 32, max idle 2, history 4, directional pruning
+    after p = 2 detections; then the integrated selection (Algorithm 3) on 6
+    of 64 partitions and the selected search over the whole pair."""
+    from paper_2204_09131_amd.search import isycos
+    st = wmi.Store(0, budget_bytes=4 << 30)
+    a, b = st.add_series(w.series[0]), st.add_series(w.series[1])
+    n = len(w.series[0])
+    bu = dict(s_min=64, s_max=4096, delta=32, sigma=0.2, max_idle=2, history=4, tau=0.05, p=2, normalize=True,
+              chunk=16384, seed=1, k=4)
+    td = dict(s_max=4096, s_min=64, sigma=0.2, tau=0.05, p=0, step_div=8, normalize=True, k=4)
+    st.bu_search(a, b, 0, 1 << 18, **bu)  # warm-up on a prefix
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    found, stats = st.bu_search(a, b, 0, n, **bu)
+    dt = time.perf_counter() - t0
+    out = {"workload": f"bottom-up search, large-search pair of {n} points", "params": bu, "seconds": dt,
+           "windows_found": int(len(found)), "covered_points": int(found["len"].astype(np.int64).sum()),
+           "pairs_per_s": stats["ordered_pairs"] / dt, **stats}
+    log(f"bu: {out}")
+    r = isycos(st, a, b, 0, n, td, bu, M=64, m=6, alpha=0.5, rho=0.5, seed=7)
+    out["isycos"] = {k: v for k, v in r.items() if k not in ("windows", "stats")}
+    out["isycos"]["windows_found"] = int(len(r["windows"]))
+    log(f"isycos: {out['isycos']}")
+    st.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,6 +450,8 @@ def main():
         log(f"large-search proxy: {out['large_search_proxy']}")
         log("top-down search over the large-search pair ...")
         out["top_down_search"] = td_bench(wmi, torch, w5)
+        log("bottom-up search and selection over the large-search pair ...")
+        out["bottom_up_search"] = bu_bench(wmi, torch, w5)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

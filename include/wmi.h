@@ -390,6 +390,61 @@ int wmi_td_search(wmi_store *store, uint32_t a, uint32_t b, uint64_t begin, uint
                   const wmi_td_params *params, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
                   wmi_search_stats *stats);
 
+/*
+ * Bottom-up search (Algorithm 2, Section 5.2): late-acceptance hill climbing
+ * over windows, with the directional noise pruning of Section 6.3.
+ * [begin, end) is cut into consecutive chunks of `chunk` points (0: one
+ * chunk); each chunk is searched by its own walker, and the walkers advance
+ * together, one batch per step (the partitioned form of Section 7.2 without
+ * overlap, so that results never overlap).  A walker repeats, from the start
+ * of the unexplored rest of its chunk:
+ *   w = the s_min first points; history L_h (h entries) := I(w); idle = 0;
+ *   while idle <= max_idle:
+ *     N = the ring of windows whose start and end differ from w's by at most
+ *         r = idle + 1 steps of delta, one of them by exactly r (8r windows),
+ *         inside the unexplored rest, s_min <= |w'| <= s_max, without the
+ *         directions pruning has closed;
+ *     best = the neighbour of largest I (first in the order start offset,
+ *         then end offset, ascending);  j = a pick of L_h;
+ *     if I(best) > L_h[j] or I(best) > I(w): w = best, idle = 0
+ *     else idle += 1;
+ *     if I(w) > L_h[j]: L_h[j] = I(w)
+ *   report w if I(w) >= sigma (normalize: sigma * ln|w|); the rest starts at
+ *   w's end.
+ * Pruning (p > 0): the ring's pure left extension (start - r delta, same end)
+ * and pure right extension are evaluated as noise triples over w; when
+ * Definition 6.2 flags a direction's extension in p consecutive steps, that
+ * direction (neighbours starting before w, or ending after it) is closed for
+ * the rest of the climb.
+ * Picks: pick number i (0, 1, ...) of the walker of chunk c is
+ *   splitmix64(seed + (c * 2^32 + i + 1) * 0x9E3779B97F4A7C15) mod h,
+ * where splitmix64(z) applies z ^= z >> 30; z *= 0xBF58476D1CE4E5B9;
+ * z ^= z >> 27; z *= 0x94D049BB133111EB; z ^= z >> 31 (Steele, Lea and
+ * Flood's SplitMix64 output function).
+ * Output, capacity and errors as for wmi_td_search ((end - begin) / s_min + 1
+ * entries suffice); layer is 0.
+ */
+typedef struct {
+    uint32_t s_min, s_max;       /* 2 <= s_min <= s_max <= WMI_MAX_WINDOW        */
+    uint32_t delta;              /* moving step, >= 1                             */
+    uint32_t max_idle;           /* T_maxIdle                                     */
+    uint32_t history;            /* h >= 1                                        */
+    uint32_t p;                  /* 0: no pruning                                 */
+    double sigma;
+    double tau;
+    uint32_t normalize;
+    uint32_t k;
+    uint32_t estimator;
+    uint32_t chunk;              /* points per walker; 0 = the whole range        */
+    uint64_t seed;
+    uint32_t flags;              /* 0 */
+    uint32_t reserved;           /* 0 */
+} wmi_bu_params;
+
+int wmi_bu_search(wmi_store *store, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
+                  const wmi_bu_params *params, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
+                  wmi_search_stats *stats);
+
 /* Copy the library's double-precision digamma table psi(1..n) (n <= 8192)
  * to host_out (for checks against an independent construction). */
 int wmi_psi_table(uint32_t n, double *host_out);

@@ -79,3 +79,101 @@ def top_down(mi, begin: int, end: int, s_max: int, s_min: int, sigma: float, tau
         layer += 1
     found.sort()
     return found
+
+
+MASK64 = (1 << 64) - 1
+GOLDEN64 = 0x9E3779B97F4A7C15
+
+
+def splitmix64(z: int) -> int:
+    """Output function of Steele, Lea and Flood's SplitMix64 generator."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def bottom_up(mi, begin: int, end: int, s_min: int, s_max: int, delta: int, sigma: float,
+              max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: bool = False,
+              chunk: int = 0, seed: int = 0, trace: list | None = None):
+    """Algorithm 2 (Section 5.2) with the directional pruning of Section 6.3,
+    chunk by chunk, one climb after another.  Readings (the library's driver
+    takes the same ones):
+    * the first window of a climb is the s_min first points of the unexplored
+      rest of the chunk; the next climb starts where the last one's window ends;
+    * the neighbourhood examined when idle = i is the ring of windows whose
+      start and end each move by at most r = i + 1 steps, one of them by
+      exactly r (the 8 and 16 windows of the paper's figure for r = 1, 2),
+      inside the rest, of s_min to s_max points, examined in order of start
+      offset then end offset; the first largest estimate is the best;
+    * the history entry compared and updated in an iteration is one pick,
+      splitmix64(seed + (chunk * 2^32 + i) * golden) mod h for the walker's
+      i-th pick (i = 1, 2, ...), the same entry for both uses;
+    * pruning: the ring's pure left and pure right extensions are noise
+      triples over w; a direction closes for the rest of the climb after p
+      consecutive examined extensions of it were noise (Definition 6.2);
+    * a window is reported when I >= sigma (normalize: sigma ln|w|).
+    ``trace`` receives every examined window as (start, end)."""
+    found = []
+    size = chunk if chunk else max(end - begin, 1)
+    c = 0
+    for c0 in range(begin, end, size):
+        c1 = min(end, c0 + size)
+        n_picks = 0
+        rest = c0
+        while c1 - rest >= s_min:
+            ws, we = rest, rest + s_min
+            if trace is not None:
+                trace.append((ws, we))
+            Iw = mi(ws, s_min)
+            hist = [Iw] * history
+            idle = 0
+            runs = {"left": 0, "right": 0}
+            closed = {"left": False, "right": False}
+            while idle <= max_idle:
+                r = idle + 1
+                best = None
+                seen = {}
+                for ds in range(-r, r + 1):
+                    for de in range(-r, r + 1):
+                        if max(abs(ds), abs(de)) != r:
+                            continue
+                        s, e = ws + ds * delta, we + de * delta
+                        if s < rest or e > c1 or not (s_min <= e - s <= s_max):
+                            continue
+                        if (closed["left"] and ds < 0) or (closed["right"] and de > 0):
+                            continue
+                        if trace is not None:
+                            trace.append((s, e))
+                        I = mi(s, e - s)
+                        if p and de == 0 and ds == -r:      # w extended on the left
+                            ext = ws - s
+                            thr = tau * math.log(ext) if normalize else tau
+                            seen["left"] = Iw > 0 and mi(s, ext) < thr and I < Iw
+                        if p and ds == 0 and de == r:       # w extended on the right
+                            ext = e - we
+                            thr = tau * math.log(ext) if normalize else tau
+                            seen["right"] = Iw > 0 and mi(we, ext) < thr and I < Iw
+                        if not math.isnan(I) and (best is None or I > best[2]):
+                            best = (s, e, I)
+                for side, noise in seen.items():
+                    runs[side] = runs[side] + 1 if noise else 0
+                n_picks += 1
+                j = splitmix64(seed + ((c << 32) + n_picks) * GOLDEN64) % history
+                if best is not None and (best[2] > hist[j] or best[2] > Iw):
+                    ws, we, Iw = best
+                    idle = 0
+                else:
+                    idle += 1
+                if Iw > hist[j]:
+                    hist[j] = Iw
+                for side in ("left", "right"):
+                    if p and runs[side] >= p:
+                        closed[side] = True
+            thr_w = sigma * math.log(we - ws) if normalize else sigma
+            if Iw >= thr_w:
+                found.append((ws, we - ws, 0, Iw))
+            rest = we
+        c += 1
+    found.sort()
+    return found

@@ -239,3 +239,282 @@ extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
         *stats_out = stats;
     return WMI_OK;
 }
+
+// --------------------------------------------------------------------------
+// bottom-up search (Algorithm 2) with directional noise pruning
+// --------------------------------------------------------------------------
+namespace {
+
+// SplitMix64 output function (Steele, Lea and Flood), used counter-based:
+// pick i of walker c draws mix(seed + (c * 2^32 + i + 1) * golden).
+uint64_t splitmix64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t bu_pick(uint64_t seed, uint64_t chunk, uint64_t i)
+{
+    return splitmix64_mix(seed + ((chunk << 32) + i + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params &prm, std::vector<wmi_result> &r,
+                wmi_search_stats &stats)
+{
+    r.assign(q.size(), wmi_result());
+    size_t i0 = 0;
+    while (i0 < q.size()) {
+        size_t i1 = i0;
+        uint64_t pts = 0;
+        while (i1 < q.size() && i1 - i0 < kChunkQueries && (i1 == i0 || pts < kChunkPoints)) {
+            pts += 2ull * q[i1].len + 2ull * q[i1].ext_len;
+            ++i1;
+        }
+        wmi_batch *bt = nullptr;
+        if (int rc = wmi_submit(st, q.data() + i0, i1 - i0, &prm, nullptr, &bt))
+            return rc;
+        int rc = wmi_read(bt, r.data() + i0);
+        (void)wmi_batch_destroy(bt);
+        if (rc)
+            return rc;
+        stats.batches++;
+        for (size_t i = i0; i < i1; ++i) {
+            const uint64_t m = q[i].len, e = q[i].ext_len;
+            if (q[i].ext_side) {
+                stats.windows_evaluated += 3;
+                stats.ordered_pairs += m * (m - 1) + e * (e - 1) + (m + e) * (m + e - 1);
+            } else {
+                stats.windows_evaluated += 1;
+                stats.ordered_pairs += m * (m - 1);
+            }
+        }
+        i0 = i1;
+    }
+    return WMI_OK;
+}
+
+struct Walker {
+    uint64_t chunk_id = 0;
+    uint64_t cursor = 0, cend = 0;  // unexplored rest of the chunk
+    uint64_t picks = 0;
+    bool climbing = false, done = false;
+    uint64_t ws = 0, we = 0;        // current window [ws, we)
+    double iw = 0.0;
+    std::vector<double> hist;
+    uint32_t idle = 0, lrun = 0, rrun = 0;
+    bool loff = false, roff = false;
+    // requests of this step
+    int pend = 0;                   // 0 none, 1 first window, 2 ring
+    std::vector<std::pair<uint64_t, uint64_t>> ring;
+    int left = -1, right = -1;      // ring entries evaluated as noise triples
+    size_t req0 = 0;
+};
+
+wmi_query window_query(uint32_t a, uint32_t b, uint64_t s, uint64_t e)
+{
+    wmi_query q{};
+    q.a = a;
+    q.b = b;
+    q.start = s;
+    q.len = (uint32_t)(e - s);
+    return q;
+}
+
+}  // namespace
+
+extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
+                             const wmi_bu_params *p, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
+                             wmi_search_stats *stats_out)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!st || !p || !n_out)
+        return fail(WMI_EINVAL, "wmi_bu_search: null argument");
+    *n_out = 0;
+    if (p->s_min < 2 || p->s_min > p->s_max || p->s_max > (uint32_t)WMI_MAX_WINDOW || p->delta < 1 ||
+        p->history < 1 || p->flags || p->reserved)
+        return fail(WMI_EINVAL, "wmi_bu_search: need 2 <= s_min <= s_max <= %d, delta >= 1, history >= 1",
+                    WMI_MAX_WINDOW);
+    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 1)
+        return fail(WMI_EINVAL, "wmi_bu_search: bad k, estimator or normalize");
+    uint64_t na = 0, nb = 0;
+    if (int rc = wmi_series_length(st, a, &na))
+        return rc;
+    if (int rc = wmi_series_length(st, b, &nb))
+        return rc;
+    if (begin > end || end > std::min(na, nb))
+        return fail(WMI_EINVAL, "wmi_bu_search: range outside the series");
+    wmi_params prm{};
+    prm.k = p->k;
+    prm.estimator = p->estimator;
+    prm.tau = p->tau;
+    prm.tau_normalize = p->normalize;
+    const bool prune = p->p > 0;
+    const uint64_t d = p->delta;
+
+    std::vector<Walker> walkers;
+    const uint64_t chunk = p->chunk ? p->chunk : std::max<uint64_t>(end - begin, 1);
+    for (uint64_t c0 = begin, id = 0; c0 < end; c0 += chunk, ++id) {
+        Walker w;
+        w.chunk_id = id;
+        w.cursor = c0;
+        w.cend = std::min(end, c0 + chunk);
+        walkers.push_back(w);
+    }
+    wmi_search_stats stats{};
+    std::vector<wmi_window> found;
+    std::vector<wmi_query> q;
+    std::vector<wmi_result> res;
+    auto threshold = [&](uint64_t m) { return p->normalize ? p->sigma * std::log((double)m) : p->sigma; };
+
+    for (;;) {
+        q.clear();
+        bool any = false;
+        for (Walker &w : walkers) {
+            w.pend = 0;
+            while (!w.done && w.pend == 0) {
+                if (!w.climbing) {
+                    if (w.cend - w.cursor < p->s_min) {
+                        w.done = true;
+                        break;
+                    }
+                    w.ws = w.cursor;
+                    w.we = w.cursor + p->s_min;
+                    w.pend = 1;
+                    w.req0 = q.size();
+                    q.push_back(window_query(a, b, w.ws, w.we));
+                    stats.windows_visited++;
+                    break;
+                }
+                // the ring of radius r = idle + 1 around w
+                const uint64_t r = w.idle + 1ull, rd = r * d;
+                w.ring.clear();
+                w.left = w.right = -1;
+                for (int64_t ds = -(int64_t)r; ds <= (int64_t)r; ++ds)
+                    for (int64_t de = -(int64_t)r; de <= (int64_t)r; ++de) {
+                        if (std::max(std::llabs(ds), std::llabs(de)) != (int64_t)r)
+                            continue;
+                        const int64_t s = (int64_t)w.ws + ds * (int64_t)d, e = (int64_t)w.we + de * (int64_t)d;
+                        if (s < (int64_t)w.cursor || e > (int64_t)w.cend || e - s < (int64_t)p->s_min ||
+                            e - s > (int64_t)p->s_max)
+                            continue;
+                        if ((w.loff && ds < 0) || (w.roff && de > 0))
+                            continue;
+                        if (prune && ds == -(int64_t)r && de == 0)
+                            w.left = (int)w.ring.size();
+                        if (prune && ds == 0 && de == (int64_t)r)
+                            w.right = (int)w.ring.size();
+                        w.ring.push_back({(uint64_t)s, (uint64_t)e});
+                    }
+                if (w.ring.empty()) {
+                    // nothing to examine: an iteration without improvement
+                    const uint64_t j = bu_pick(p->seed, w.chunk_id, w.picks++) % p->history;
+                    w.idle++;
+                    if (w.iw > w.hist[j])
+                        w.hist[j] = w.iw;
+                    if (w.idle > p->max_idle) {
+                        if (w.iw >= threshold(w.we - w.ws))
+                            found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
+                        w.cursor = w.we;
+                        w.climbing = false;
+                    }
+                    continue;
+                }
+                w.pend = 2;
+                w.req0 = q.size();
+                for (size_t i = 0; i < w.ring.size(); ++i) {
+                    wmi_query x = window_query(a, b, w.ring[i].first, w.ring[i].second);
+                    if ((int)i == w.left) {  // base w, extension on the left
+                        x = window_query(a, b, w.ws, w.we);
+                        x.ext_len = (uint32_t)rd;
+                        x.ext_side = -1;
+                    } else if ((int)i == w.right) {
+                        x = window_query(a, b, w.ws, w.we);
+                        x.ext_len = (uint32_t)rd;
+                        x.ext_side = 1;
+                    }
+                    q.push_back(x);
+                }
+                stats.windows_visited += w.ring.size();
+            }
+            any = any || !w.done;
+        }
+        if (!any)
+            break;
+        if (q.empty())
+            continue;
+        if (int rc = run_queries(st, q, prm, res, stats))
+            return rc;
+        for (Walker &w : walkers) {
+            if (w.pend == 1) {
+                w.iw = res[w.req0].mi_base;
+                w.hist.assign(p->history, w.iw);
+                w.idle = 0;
+                w.lrun = w.rrun = 0;
+                w.loff = w.roff = false;
+                w.climbing = true;
+            } else if (w.pend == 2) {
+                int best = -1;
+                double ib = 0.0;
+                for (size_t i = 0; i < w.ring.size(); ++i) {
+                    const wmi_result &x = res[w.req0 + i];
+                    const double v = ((int)i == w.left || (int)i == w.right) ? x.mi_union : x.mi_base;
+                    if (!std::isnan(v) && (best < 0 || v > ib)) {
+                        best = (int)i;
+                        ib = v;
+                    }
+                }
+                if (w.left >= 0) {
+                    const bool nz = (res[w.req0 + w.left].flags & WMI_F_NOISE) != 0;
+                    stats.noise_detections += nz;
+                    w.lrun = nz ? w.lrun + 1 : 0;
+                }
+                if (w.right >= 0) {
+                    const bool nz = (res[w.req0 + w.right].flags & WMI_F_NOISE) != 0;
+                    stats.noise_detections += nz;
+                    w.rrun = nz ? w.rrun + 1 : 0;
+                }
+                const uint64_t j = bu_pick(p->seed, w.chunk_id, w.picks++) % p->history;
+                if (best >= 0 && (ib > w.hist[j] || ib > w.iw)) {
+                    w.ws = w.ring[best].first;
+                    w.we = w.ring[best].second;
+                    w.iw = ib;
+                    w.idle = 0;
+                } else {
+                    w.idle++;
+                }
+                if (w.iw > w.hist[j])
+                    w.hist[j] = w.iw;
+                if (prune && !w.loff && w.lrun >= p->p) {
+                    w.loff = true;
+                    stats.noise_skips++;
+                }
+                if (prune && !w.roff && w.rrun >= p->p) {
+                    w.roff = true;
+                    stats.noise_skips++;
+                }
+                if (w.idle > p->max_idle) {
+                    if (w.iw >= threshold(w.we - w.ws))
+                        found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
+                    w.cursor = w.we;
+                    w.climbing = false;
+                }
+            }
+        }
+    }
+    std::sort(found.begin(), found.end(),
+              [](const wmi_window &x, const wmi_window &y) { return x.start < y.start; });
+    *n_out = found.size();
+    if (found.size() > capacity)
+        return fail(WMI_EINVAL, "wmi_bu_search: %llu windows found, room for %llu", (unsigned long long)found.size(),
+                    (unsigned long long)capacity);
+    if (!found.empty() && !host_out)
+        return fail(WMI_EINVAL, "wmi_bu_search: null output");
+    if (!found.empty())
+        std::memcpy(host_out, found.data(), found.size() * sizeof(wmi_window));
+    stats.layers = 1;
+    stats.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats_out)
+        *stats_out = stats;
+    return WMI_OK;
+}

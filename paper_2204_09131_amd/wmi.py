@@ -53,7 +53,7 @@ EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destr
            "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
            "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
-           "wmi_td_search")
+           "wmi_td_search", "wmi_bu_search")
 REPLAY_DIRECT = 1
 
 
@@ -109,6 +109,14 @@ class _TdParams(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class _BuParams(ctypes.Structure):
+    _fields_ = [("s_min", ctypes.c_uint32), ("s_max", ctypes.c_uint32), ("delta", ctypes.c_uint32),
+                ("max_idle", ctypes.c_uint32), ("history", ctypes.c_uint32), ("p", ctypes.c_uint32),
+                ("sigma", ctypes.c_double), ("tau", ctypes.c_double), ("normalize", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("estimator", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class _SearchStats(ctypes.Structure):
     _fields_ = [("layers", ctypes.c_uint64), ("windows_visited", ctypes.c_uint64),
                 ("windows_evaluated", ctypes.c_uint64), ("ordered_pairs", ctypes.c_uint64),
@@ -158,6 +166,7 @@ def lib():
         "wmi_server_clock_us": ([vp], ctypes.c_double),
         "wmi_server_destroy": ([vp], ctypes.c_int),
         "wmi_td_search": ([vp, u32, u32, u64, u64, P(_TdParams), vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
+        "wmi_bu_search": ([vp, u32, u32, u64, u64, P(_BuParams), vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -351,6 +360,22 @@ class Store:
         n = ctypes.c_uint64()
         st = _SearchStats()
         _check(lib().wmi_td_search(self.h, int(a), int(b), int(begin), int(end), ctypes.byref(prm),
+                                   out.ctypes.data, cap, ctypes.byref(n), ctypes.byref(st)))
+        return out[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
+
+    def bu_search(self, a: int, b: int, begin: int, end: int, s_min: int, s_max: int, delta: int, sigma: float,
+                  max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: bool = False,
+                  chunk: int = 0, seed: int = 0, k: int = 4, estimator: int = 0):
+        """Bottom-up search (wmi_bu_search): correlated windows (WINDOW_DTYPE,
+        ascending start) and the search counters."""
+        prm = _BuParams(int(s_min), int(s_max), int(delta), int(max_idle), int(history), int(p), float(sigma),
+                        float(tau), 1 if normalize else 0, int(k), int(estimator), int(chunk),
+                        int(seed) & 0xFFFFFFFFFFFFFFFF, 0, 0)
+        cap = max(1, (int(end) - int(begin)) // max(int(s_min), 1) + 1)
+        out = np.zeros(cap, dtype=WINDOW_DTYPE)
+        n = ctypes.c_uint64()
+        st = _SearchStats()
+        _check(lib().wmi_bu_search(self.h, int(a), int(b), int(begin), int(end), ctypes.byref(prm),
                                    out.ctypes.data, cap, ctypes.byref(n), ctypes.byref(st)))
         return out[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
 

@@ -86,3 +86,62 @@ def test_td_driver_matches_sequential_rule(wmi, orc, case):
         assert stats["noise_detections"] >= stats["noise_skips"]
     if s_max % max(1, s_max // div):
         assert stats["batches"] > stats["layers"]  # follow-up batches ran
+
+
+def oracle_bu(orc, x, y, **kw):
+    cache = {}
+
+    def mi(s, m):
+        key = (s, m)
+        if key not in cache:
+            cache[key] = orc.window_mi(x[s:s + m], y[s:s + m], k=kw.get("k", 4))
+        return cache[key]
+    args = {k: v for k, v in kw.items() if k != "k"}
+    return search.bottom_up(mi, **args), cache
+
+
+BU_CASES = [
+    # (series seed, n, chunk, s_min, s_max, delta, max_idle, history, sigma, tau, p, normalize, seed)
+    (21, 4096, 1024, 32, 256, 16, 2, 4, 0.30, 0.075, 0, False, 7),
+    (22, 4096, 2048, 32, 256, 16, 2, 4, 0.30, 0.075, 2, False, 8),
+    (23, 6000, 1500, 48, 384, 24, 1, 3, 0.15, 0.04, 1, True, 9),
+    (24, 3000, 0, 64, 512, 32, 2, 5, 0.25, 0.06, 2, False, 10),
+]
+
+
+@pytest.mark.parametrize("case", BU_CASES)
+def test_bu_driver_matches_sequential_rule(wmi, orc, case):
+    seed, n, chunk, s_min, s_max, delta, idle, h, sigma, tau, p, norm, rs = case
+    x, y = synth.cfg2_pair(n, seed)
+    st = wmi.Store(0)
+    a, b = st.add_series(x), st.add_series(y)
+    kw = dict(s_min=s_min, s_max=s_max, delta=delta, sigma=sigma, max_idle=idle, history=h, tau=tau, p=p,
+              normalize=norm, chunk=chunk, seed=rs)
+    got, stats = st.bu_search(a, b, 0, n, **kw)
+    st.close()
+    ref, cache = oracle_bu(orc, x, y, begin=0, end=n, **kw)
+    log(f"bu case {case}: {len(ref)} windows; stats {stats}; {len(cache)} distinct windows on the CPU")
+    # comparisons between estimates closer than 1e-9 could go either way
+    vals = np.sort(np.array([v for v in cache.values() if not math.isnan(v)]))
+    assert np.min(np.diff(np.unique(vals))) > TOL
+    assert [(int(s), int(m)) for s, m, _, _ in ref] == [(int(r["start"]), int(r["len"])) for r in got]
+    if len(ref):
+        assert np.max(np.abs(np.array([v for *_, v in ref]) - got["mi"])) <= TOL
+
+
+def test_isycos_selection_runs_the_selected_search(wmi):
+    from paper_2204_09131_amd.search import isycos
+    x, y = synth.cfg2_pair(65536, 31)
+    st = wmi.Store(0)
+    a, b = st.add_series(x), st.add_series(y)
+    td = dict(s_max=1024, s_min=64, sigma=0.2, tau=0.05, p=0, step_div=8, normalize=True)
+    bu = dict(s_min=64, s_max=1024, delta=32, sigma=0.2, max_idle=2, history=4, tau=0.05, p=2, normalize=True,
+              chunk=4096, seed=3)
+    r = isycos(st, a, b, 0, 65536, td, bu, M=16, m=4, alpha=0.5, rho=0.5, seed=5)
+    log(f"isycos: selected {r['selected']}, scores {r['nscore_td']:.3f} / {r['nscore_bu']:.3f}, "
+        f"{len(r['windows'])} windows")
+    ref, _ = (st.td_search(a, b, 0, 65536, **td) if r["selected"] == "top-down"
+              else st.bu_search(a, b, 0, 65536, **bu))
+    assert np.array_equal(ref, r["windows"])
+    assert (r["nscore_td"] > r["nscore_bu"]) == (r["selected"] == "top-down")
+    st.close()

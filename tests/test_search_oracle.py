@@ -90,3 +90,50 @@ def test_normalized_thresholds():
     v = 0.45 * math.log(64)
     found = search.top_down(lambda t, m: v, 0, 128, 128, 64, 0.45, normalize=True)
     assert [(s, m) for s, m, _, _ in found] == [(0, 64), (64, 64)]
+
+
+def test_splitmix64_reference_value():
+    # first output of SplitMix64 seeded with 0 (the published reference
+    # generator's value): mix(0 + golden)
+    assert search.splitmix64(0 + search.GOLDEN64) == 0xE220A8397B1DCDAF
+
+
+def test_bottom_up_hill_climb_by_hand():
+    # I = |w| / 1000, one history entry (plain hill climbing), s_min 64,
+    # s_max 128, step 16, max_idle 1 on [0, 300): each climb grows its end to
+    # 128 points, then two rings bring nothing larger; climbs start at 0 and
+    # 128, and 44 points are left.
+    found = search.bottom_up(lambda s, m: m / 1000.0, 0, 300, 64, 128, 16, 0.1, max_idle=1, history=1)
+    assert [(s, m) for s, m, _, _ in found] == [(0, 128), (128, 128)]
+    # below the threshold nothing is reported
+    assert search.bottom_up(lambda s, m: m / 1000.0, 0, 300, 64, 128, 16, 0.2, max_idle=1, history=1) == []
+
+
+def test_bottom_up_first_largest_wins_and_climbs_stay_in_their_chunk():
+    trace = []
+    found = search.bottom_up(lambda s, m: m / 1000.0, 0, 600, 64, 128, 16, 0.1, max_idle=1, history=1,
+                             chunk=300, trace=trace)
+    assert [(s, m) for s, m, _, _ in found] == [(0, 128), (128, 128), (300, 128), (428, 128)]
+    assert all(e <= 300 or s >= 300 for s, e in trace)
+
+
+def test_bottom_up_left_pruning_by_hand():
+    # I = start / 1000 for windows of 32 points or more, 0 below: moving right
+    # pays, and every pure left extension is noise (its 16 new points score
+    # 0 < tau, the union scores below w, and I(w) > 0 once w left 0), while no
+    # right extension is (its union scores the same as w).  Range [0, 96),
+    # s_min 32, s_max 64, step 16, max_idle 0, one history entry, p = 1: the
+    # left side closes in the second ring, and the climb ends at [64, 96).
+    def mi(s, m):
+        return s / 1000.0 if m >= 32 else 0.0
+    trace = []
+    found = search.bottom_up(mi, 0, 96, 32, 64, 16, 0.05, max_idle=0, history=1, tau=0.1, p=1, trace=trace)
+    assert [(s, m) for s, m, _, _ in found] == [(64, 32)]
+    assert trace == [(0, 32),
+                     (0, 48), (16, 48),                               # ring of [0, 32)
+                     (0, 32), (0, 48), (0, 64), (16, 64), (32, 64),   # ring of [16, 48): left noise
+                     (32, 80), (48, 80),                              # ring of [32, 64), left closed
+                     (48, 96), (64, 96)]                              # ring of [48, 80); [64, 96)'s is empty
+    trace0 = []
+    search.bottom_up(mi, 0, 96, 32, 64, 16, 0.05, max_idle=0, history=1, tau=0.1, p=0, trace=trace0)
+    assert trace0[8:11] == [(16, 48), (16, 64), (16, 80)]  # without pruning the left side stays open
