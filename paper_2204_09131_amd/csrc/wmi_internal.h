@@ -12,8 +12,9 @@
 //                        kernel, one launch per window)
 //   u32      ready[W]    per window: sorted marginals written
 //   QDesc    qd[Qn]      one per query: its first window, window count, tau
-//   int32    sorted[2*P] per split window, its x and y grid integers in
-//                        ascending order (P = sum of their m)
+//   int32    sorted[3*P] per split window (P = sum of their m): its points
+//                        in x order (keys with index, and their y) and its
+//                        y grid integers in ascending order
 //   u64      acc[W]      fixed-point digamma sums (2^-44), integer atomics
 //   u32      wdone[W], qdone[Qn], counter[1]   completion and work counters
 //   double   wmi[W]; u32 wflags[W]           per-window estimate and flags
@@ -42,6 +43,13 @@ constexpr uint32_t kItemLocal = 0x80000000u;
 constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
 constexpr uint32_t kErrWait = 1u;            // error word: a dependency wait gave up
+// Sorted data of a split window (kSortedWords x m words from sorted_off):
+//   [0, m)   32-bit keys: ((X - min_x) << nb) | i in ascending order (the
+//            points in x order, each with its index); with nb == 0 (64-bit
+//            keys) the grid integers X in ascending order
+//   [m, 2m)  (Y - min_y) << nb of the point at each sorted-x position
+//   [2m, 3m) the grid integers Y in ascending order
+constexpr int kSortedWords = 3;
 
 struct WinDesc {            // 32 bytes
     const float *x;         // series a + window start

@@ -61,6 +61,15 @@ __device__ __forceinline__ uint32_t sad_key(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
+// The same with the index c in a vector register (candidates in x order carry
+// their own index).
+__device__ __forceinline__ uint32_t sad_key_v(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Workgroup barrier after this wave's LDS accesses have completed.  The
 // wait is explicit: the compiler's own wait before a barrier at the head of
 // a loop (reached along the back edge from LDS stores) was found missing, and
@@ -272,17 +281,43 @@ __device__ void sort_marginal(const float *v, int m, int32_t *scratch, int32_t *
     block_sync();
 }
 
-// Write the sorted marginals of window w to HBM, make them visible to every
-// CU, then raise the window's ready flag.
-__device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf)
+__device__ WinAux window_aux(const WinDesc &d, int32_t *s_red);
+
+// Write the sorted data of split window w to HBM (layout at kSortedWords),
+// make it visible to every CU, then raise the window's ready flag.
+__device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_t *s_red)
 {
     const WinDesc d = a.win[w];
     const int m = (int)d.m;
-    int32_t *out = a.sorted + 2ull * d.sorted_off;
+    const int tid = threadIdx.x;
+    int32_t *out = a.sorted + (uint64_t)kSortedWords * d.sorted_off;
     int32_t *scratch = reinterpret_cast<int32_t *>(buf);
-    sort_marginal(d.x, m, scratch, out);
-    sort_marginal(d.y, m, scratch, out + m);
-    __threadfence();  // release: this wave's stores reach every XCD before the flag
+    const WinAux ax = window_aux(d, s_red);
+    if (ax.nb) {
+        // keys ((X - min_x) << nb) | i; the sign bit is flipped for the signed
+        // sort so that signed order is unsigned key order
+        int P = 1;
+        while (P < m)
+            P <<= 1;
+        uint32_t off = 0;
+        block_sync();
+        for (int i = tid; i < P; i += kBlock)
+            scratch[i] = i < m ? (int32_t)((((uint32_t)(grid_int(d.x[i], off) - ax.min_x) << ax.nb) | (uint32_t)i) ^
+                                           0x80000000u)
+                               : INT32_MAX;
+        bitonic_lds<kMaxWindow / (2 * kBlock), 1>(scratch, nullptr, (uint32_t)P, (uint32_t)P);
+        const uint32_t mask = (1u << ax.nb) - 1u;
+        for (int s = tid; s < m; s += kBlock) {
+            const uint32_t key = (uint32_t)scratch[s] ^ 0x80000000u;
+            const uint32_t j = key & mask;
+            out[s] = (int32_t)key;
+            out[m + s] = (int32_t)((uint32_t)(grid_int(d.y[j], off) - ax.min_y) << ax.nb);
+        }
+    } else {
+        sort_marginal(d.x, m, scratch, out);
+    }
+    sort_marginal(d.y, m, scratch, out + 2 * m);
+    __threadfence();
     block_sync();
     if (threadIdx.x == 0)
         atomicExch(&a.ready[w], 1u);
@@ -476,10 +511,10 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
     return ax;
 }
 
-// Wait until window w's sorted marginals are in HBM.  The prep item has a
-// lower index than every split item, so a running workgroup already holds it
-// and it waits on nothing: the wait ends.  A poll limit turns a broken
-// dependency into an error report instead of a hang.
+// Wait until window w's sorted data is in HBM.  The prep item has a lower
+// index than every split item, so a running workgroup already holds it and it
+// waits on nothing: the wait ends.  A poll limit turns a broken dependency
+// into an error report instead of a hang.
 __device__ void wait_ready(const LaunchArgs &a, uint32_t w)
 {
     if (threadIdx.x == 0) {
@@ -506,58 +541,8 @@ __device__ __forceinline__ uint32_t key_coord(const float *v, int i, int32_t mn,
     return (uint32_t)(grid_int(v[i], off) - mn) << nb;
 }
 
-// Scan candidates [jlo, jhi) (global indices; LDS holds [c0, c0 + chunk))
-// with 32-bit keys into k-entry lists.  Slot MQ (if >= 0) is the one whose
-// own point can appear in this range: its key for j == self is replaced by
-// the largest key, so the point never enters its own list.
-template <int K, int Q, int MQ>
-__device__ __forceinline__ void scan_seg(const uint32_t *__restrict__ cand, int c0, int jlo, int jhi,
-                                         const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
-                                         const uint32_t (&self)[Q], uint32_t (&top)[Q][K])
-{
-    if (jlo >= jhi)
-        return;
-    const uint4 *c4 = reinterpret_cast<const uint4 *>(cand);
-    int j = jlo;
-    if ((j - c0) & 1) {  // keep 16-byte reads aligned (segment starts are even in practice)
-        const uint32_t cx = cand[2 * (j - c0)], cy = cand[2 * (j - c0) + 1];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            uint32_t k0 = tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j));
-            if (q == MQ)
-                k0 = (uint32_t)j == self[q] ? 0xFFFFFFFFu : k0;
-            insert_sorted<K>(top[q], k0);
-        }
-        ++j;
-    }
-    for (; j + 1 < jhi; j += 2) {
-        uint4 c = c4[(j - c0) >> 1];
-        const uint32_t j0 = (uint32_t)j;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            uint32_t k0 = tmax(sad_key(qx[q], c.x, j0), sad_key(qy[q], c.y, j0));
-            uint32_t k1 = tmax(sad_key(qx[q], c.z, j0 + 1u), sad_key(qy[q], c.w, j0 + 1u));
-            if (q == MQ) {
-                k0 = j0 == self[q] ? 0xFFFFFFFFu : k0;
-                k1 = j0 + 1u == self[q] ? 0xFFFFFFFFu : k1;
-            }
-            insert_sorted<K>(top[q], k0);
-            insert_sorted<K>(top[q], k1);
-        }
-    }
-    if (j < jhi) {
-        const uint32_t cx = cand[2 * (j - c0)], cy = cand[2 * (j - c0) + 1];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            uint32_t k0 = tmax(sad_key(qx[q], cx, (uint32_t)j), sad_key(qy[q], cy, (uint32_t)j));
-            if (q == MQ)
-                k0 = (uint32_t)j == self[q] ? 0xFFFFFFFFu : k0;
-            insert_sorted<K>(top[q], k0);
-        }
-    }
-}
-
-// Same with 64-bit keys (d << 12 | j) over offset grid integers.
+// Scan candidates [c0, c0 + cn) (LDS holds their grid-integer pairs) with
+// 64-bit keys (d << 12 | j) into (k+1)-entry lists.
 template <int K, int Q>
 __device__ __forceinline__ void scan_wide(const uint32_t *__restrict__ cand, int c0, int cn,
                                           const uint32_t (&qx)[Q], const uint32_t (&qy)[Q],
@@ -613,90 +598,56 @@ __device__ __forceinline__ void split_radii(const T (&top)[K + 1], T self, int s
     split_radii_k<K, T>(nbk, shift, mask, d, ax, qx, qy, est, rx, ry);
 }
 
+// Split item of a window whose value range needs 64-bit keys (nb == 0): Q
+// query points per thread (points q0 + tid + q * kBlock), all m candidates
+// streamed through LDS as grid integers, then counts over the sorted
+// marginals.
 template <int K, int Q>
-__device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w, const WinDesc &d, const WinAux &ax,
-                                                int q0, uint32_t *buf)
+__device__ __forceinline__ long long split_body_wide(const LaunchArgs &a, uint32_t w, const WinDesc &d,
+                                                     const WinAux &ax, int q0, uint32_t *buf)
 {
     constexpr int S = K + 1;
     const int m = (int)d.m;
     const int tid = threadIdx.x;
-    const uint32_t nb = ax.nb;
     uint32_t qx[Q], qy[Q], rx[Q], ry[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = min(q0 + tid + q * kBlock, m - 1);
-        qx[q] = key_coord(d.x, i, ax.min_x, nb);
-        qy[q] = key_coord(d.y, i, ax.min_y, nb);
+        qx[q] = key_coord(d.x, i, ax.min_x, 0u);
+        qy[q] = key_coord(d.y, i, ax.min_y, 0u);
     }
     // ---- neighbours: candidates stream through LDS in chunks
-    if (nb) {
-        // k-entry lists; the point itself is masked inside its wave's band of
-        // 64 consecutive candidates (queries of a wave are consecutive points)
-        uint32_t top[Q][K], self[Q];
+    unsigned long long top[Q][S];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            self[q] = (uint32_t)(q0 + tid + q * kBlock);
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int r = 0; r < K; ++r)
-                top[q][r] = 0xFFFFFFFFu;
+        for (int r = 0; r < S; ++r)
+            top[q][r] = ~0ull;
+    for (int c0 = 0; c0 < m; c0 += kChunk) {
+        const int cn = min(kChunk, m - c0);
+        block_sync();
+        for (int i = tid; i < cn; i += kBlock) {
+            buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, 0u);
+            buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, 0u);
         }
-        const int band0 = __builtin_amdgcn_readfirstlane(q0 + (tid & ~63));  // wave-uniform
-        const int band1 = band0 + kBlock;
-        for (int c0 = 0; c0 < m; c0 += kChunk) {
-            const int cn = min(kChunk, m - c0), e = c0 + cn;
-            block_sync();
-            for (int i = tid; i < cn; i += kBlock) {
-                buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, nb);
-                buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, nb);
-            }
-            block_sync();
-            scan_seg<K, Q, -1>(buf, c0, c0, min(e, band0), qx, qy, self, top);
-            scan_seg<K, Q, 0>(buf, c0, max(c0, band0), min(e, band0 + 64), qx, qy, self, top);
-            if (Q == 1) {
-                scan_seg<K, Q, -1>(buf, c0, max(c0, band0 + 64), e, qx, qy, self, top);
-            } else {
-                scan_seg<K, Q, -1>(buf, c0, max(c0, band0 + 64), min(e, band1), qx, qy, self, top);
-                scan_seg<K, Q, (Q > 1 ? 1 : -1)>(buf, c0, max(c0, band1), min(e, band1 + 64), qx, qy, self, top);
-                scan_seg<K, Q, -1>(buf, c0, max(c0, band1 + 64), e, qx, qy, self, top);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            split_radii_k<K, uint32_t>(top[q], (int)nb, (1u << nb) - 1u, d, ax, qx[q], qy[q], a.estimator, rx[q],
-                                       ry[q]);
-    } else {
-        unsigned long long top[Q][S];
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int r = 0; r < S; ++r)
-                top[q][r] = ~0ull;
-        for (int c0 = 0; c0 < m; c0 += kChunk) {
-            const int cn = min(kChunk, m - c0);
-            block_sync();
-            for (int i = tid; i < cn; i += kBlock) {
-                buf[2 * i] = key_coord(d.x, c0 + i, ax.min_x, 0u);
-                buf[2 * i + 1] = key_coord(d.y, c0 + i, ax.min_y, 0u);
-            }
-            block_sync();
-            scan_wide<K, Q>(buf, c0, cn, qx, qy, top);
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            split_radii<K, unsigned long long>(top[q], (unsigned long long)min(q0 + tid + q * kBlock, m - 1), 12,
-                                               0xFFFu, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
+        block_sync();
+        scan_wide<K, Q>(buf, c0, cn, qx, qy, top);
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        split_radii<K, unsigned long long>(top[q], (unsigned long long)min(q0 + tid + q * kBlock, m - 1), 12,
+                                           0xFFFu, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
     // ---- marginal counts over the sorted marginals, chunk by chunk
     wait_ready(a, w);
     int32_t xi[Q], yi[Q];
     int hx[Q], lx[Q], hy[Q], ly[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        xi[q] = (int32_t)(qx[q] >> nb) + ax.min_x;
-        yi[q] = (int32_t)(qy[q] >> nb) + ax.min_y;
+        xi[q] = (int32_t)qx[q] + ax.min_x;
+        yi[q] = (int32_t)qy[q] + ax.min_y;
         hx[q] = lx[q] = hy[q] = ly[q] = 0;
     }
-    const int32_t *src = a.sorted + 2ull * d.sorted_off;
+    const int32_t *src = a.sorted + (uint64_t)kSortedWords * d.sorted_off;
     int32_t *sx = reinterpret_cast<int32_t *>(buf);
     int32_t *sy = sx + kChunk;
     int32_t vx[2 * Q], vy[2 * Q];
@@ -708,7 +659,7 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
         block_sync();
         for (int i = tid; i < cn; i += kBlock) {
             sx[i] = src[c0 + i];
-            sy[i] = src[m + c0 + i];
+            sy[i] = src[2 * m + c0 + i];
         }
         block_sync();
         int cxs[2 * Q], cys[2 * Q];
@@ -739,6 +690,234 @@ __device__ __forceinline__ long long split_body(const LaunchArgs &a, uint32_t w,
     return part;
 }
 
+// --------------------------------------------------------------------------
+// split items over the x order: neighbours by an outward scan
+// --------------------------------------------------------------------------
+// A split item takes 512 consecutive positions of its window's x order, two
+// adjacent ones per thread, so a wave holds 128 queries adjacent in x.  Each
+// wave scans candidates in x order: its own block first (the queries' own
+// points masked), then outwards, a chunk to the right and a chunk to the left
+// in turn.  A candidate with |dx| larger than a query's current k-th distance
+// cannot enter its list, and |dx| only grows further out, so a side stops once
+// every query of the wave is past that point; the k smallest keys, and so the
+// results, are those of the full scan.  Candidates travel through a private
+// LDS chunk of the wave as (Ux, Uy, index); no workgroup barrier is involved.
+constexpr int kWaveChunk = 128;
+
+__device__ __forceinline__ void stage_wave(uint4 *wb, const uint32_t *KX, const uint32_t *YS, int c0, int cnt,
+                                           uint32_t mask)
+{
+    const int lane = threadIdx.x & 63;
+    asm volatile("" ::: "memory");
+    for (int i = lane; i < cnt; i += 64) {
+        const uint32_t key = KX[c0 + i];
+        wb[i] = make_uint4(key & ~mask, YS[c0 + i], key & mask, 0u);
+    }
+    // the chunk is written by the whole wave before any lane reads it
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+}
+
+template <int K, bool SELF>
+__device__ __forceinline__ void scan_wave(const uint4 *__restrict__ wb, int cnt, const uint32_t (&qx)[2],
+                                          const uint32_t (&qy)[2], const uint32_t (&qj)[2], uint32_t (&top)[2][K])
+{
+#pragma unroll 2
+    for (int i = 0; i < cnt; ++i) {
+        const uint4 c = wb[i];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            uint32_t k = tmax(sad_key_v(qx[t], c.x, c.z), sad_key_v(qy[t], c.y, c.z));
+            if (SELF)
+                k = c.z == qj[t] ? 0xFFFFFFFFu : k;
+            insert_sorted<K>(top[t], k);
+        }
+    }
+}
+
+// Does some live query of the wave still need candidates at x-distance
+// dist[t] (in key units) on a side?  dist > (k-th key | mask) means its
+// distance exceeds the k-th neighbour's.
+template <int K>
+__device__ __forceinline__ bool side_open(const bool (&live)[2], const uint32_t (&dist)[2], const uint32_t (&top)[2][K],
+                                          uint32_t mask)
+{
+    bool need = false;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+        need = need || (live[t] && dist[t] <= (top[t][K - 1] | mask));
+    return __ballot(need) != 0ull;
+}
+
+// #{S[0..n) < v} for ascending 32-bit keys (thresholds up to 2^32) and
+// #{T[0..n) < u} for ascending integers, NX of each, interleaved.
+template <int NX>
+__device__ __forceinline__ void count_lt_keys(const uint32_t *sx, const int32_t *sy, int n, const uint64_t (&vx)[NX],
+                                              const int32_t (&vy)[NX], int (&cx)[NX], int (&cy)[NX])
+{
+    int bx[NX], by[NX];
+#pragma unroll
+    for (int t = 0; t < NX; ++t)
+        bx[t] = by[t] = 0;
+    while (n > 1) {
+        const int half = n >> 1;
+        uint32_t ex[NX];
+        int32_t ey[NX];
+#pragma unroll
+        for (int t = 0; t < NX; ++t) {
+            ex[t] = sx[bx[t] + half];
+            ey[t] = sy[by[t] + half];
+        }
+#pragma unroll
+        for (int t = 0; t < NX; ++t) {
+            bx[t] = (uint64_t)ex[t] < vx[t] ? bx[t] + half : bx[t];
+            by[t] = ey[t] < vy[t] ? by[t] + half : by[t];
+        }
+        n -= half;
+    }
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+        cx[t] = bx[t] + ((uint64_t)sx[bx[t]] < vx[t] ? 1 : 0);
+        cy[t] = by[t] + (sy[by[t]] < vy[t] ? 1 : 0);
+    }
+}
+
+// Key threshold of "X - min_x < v" for keys ((X - min_x) << nb) | i.
+__device__ __forceinline__ uint64_t key_below(int64_t v, uint32_t nb)
+{
+    if (v <= 0)
+        return 0ull;
+    if (v >= (1ll << (32 - nb)))
+        return 1ull << 32;
+    return (uint64_t)v << nb;
+}
+
+template <int K>
+__device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const WinDesc &d, const WinAux &ax, int q0,
+                                       uint32_t *buf)
+{
+    const int m = (int)d.m;
+    const int tid = threadIdx.x;
+    const uint32_t nb = ax.nb, mask = (1u << nb) - 1u;
+    wait_ready(a, w);
+    const uint32_t *KX = reinterpret_cast<const uint32_t *>(a.sorted + (uint64_t)kSortedWords * d.sorted_off);
+    const uint32_t *YS = KX + m;
+    const int32_t *SY = reinterpret_cast<const int32_t *>(KX + 2 * m);
+    uint32_t qx[2], qy[2], qj[2], top[2][K];
+    bool live[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int p = q0 + 2 * tid + t;
+        live[t] = p < m;
+        const int pc = min(p, m - 1);
+        const uint32_t key = KX[pc];
+        qx[t] = key & ~mask;
+        qj[t] = key & mask;
+        qy[t] = YS[pc];
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            top[t][r] = 0xFFFFFFFFu;
+    }
+    // ---- neighbours, wave by wave
+    {
+        const int wave = tid >> 6;
+        uint4 *wb = reinterpret_cast<uint4 *>(buf) + wave * kWaveChunk;
+        const int w_lo = __builtin_amdgcn_readfirstlane(q0 + 128 * wave);
+        if (w_lo < m) {
+            const int w_hi = min(m, w_lo + 128);
+            stage_wave(wb, KX, YS, w_lo, w_hi - w_lo, mask);
+            scan_wave<K, true>(wb, w_hi - w_lo, qx, qy, qj, top);
+            uint32_t dist[2];
+            const uint32_t redge = wb[w_hi - w_lo - 1].x, ledge = wb[0].x;
+            int r = w_hi, l = w_lo;
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                dist[t] = redge - qx[t];
+            bool ropen = r < m && side_open<K>(live, dist, top, mask);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                dist[t] = qx[t] - ledge;
+            bool lopen = l > 0 && side_open<K>(live, dist, top, mask);
+            while (ropen || lopen) {
+                if (ropen) {
+                    const int cnt = min(kWaveChunk, m - r);
+                    stage_wave(wb, KX, YS, r, cnt, mask);
+                    scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
+                    const uint32_t e = wb[cnt - 1].x;
+                    r += cnt;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        dist[t] = e - qx[t];
+                    ropen = r < m && side_open<K>(live, dist, top, mask);
+                }
+                if (lopen) {
+                    const int cnt = min(kWaveChunk, l);
+                    stage_wave(wb, KX, YS, l - cnt, cnt, mask);
+                    scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
+                    const uint32_t e = wb[0].x;
+                    l -= cnt;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        dist[t] = qx[t] - e;
+                    lopen = l > 0 && side_open<K>(live, dist, top, mask);
+                }
+            }
+        }
+    }
+    uint32_t rx[2], ry[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+        split_radii_k<K, uint32_t>(top[t], (int)nb, mask, d, ax, qx[t], qy[t], a.estimator, rx[t], ry[t]);
+    // ---- marginal counts: x over the keys, y over the sorted integers
+    uint64_t vx[4];
+    int32_t vy[4];
+    const int64_t o = a.estimator == 0 ? 1 : 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t xr = (int64_t)(qx[t] >> nb), e = (int64_t)rx[t];
+        vx[2 * t] = key_below(xr + e + o, nb);
+        vx[2 * t + 1] = key_below(xr - e + 1 - o, nb);
+        const int32_t yi = (int32_t)(qy[t] >> nb) + ax.min_y, ey = (int32_t)ry[t];
+        vy[2 * t] = yi + ey + (int32_t)o;
+        vy[2 * t + 1] = yi - ey + 1 - (int32_t)o;
+    }
+    int hx[2] = {0, 0}, lx[2] = {0, 0}, hy[2] = {0, 0}, ly[2] = {0, 0};
+    uint32_t *sx = buf;
+    int32_t *sy = reinterpret_cast<int32_t *>(buf + kChunk);
+    for (int c0 = 0; c0 < m; c0 += kChunk) {
+        const int cn = min(kChunk, m - c0);
+        block_sync();
+        for (int i = tid; i < cn; i += kBlock) {
+            sx[i] = KX[c0 + i];
+            sy[i] = SY[c0 + i];
+        }
+        block_sync();
+        int cxs[4], cys[4];
+        count_lt_keys<4>(sx, sy, cn, vx, vy, cxs, cys);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            hx[t] += cxs[2 * t];
+            lx[t] += cxs[2 * t + 1];
+            hy[t] += cys[2 * t];
+            ly[t] += cys[2 * t + 1];
+        }
+    }
+    long long part = 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (!live[t])
+            continue;
+        int cx, cy;
+        part += point_terms(a, hx[t], lx[t], hy[t], ly[t], (int32_t)rx[t], cx, cy);
+        if (a.dbg_nx) {
+            a.dbg_nx[qj[t]] = (uint32_t)cx;
+            a.dbg_ny[qj[t]] = (uint32_t)cy;
+            a.dbg_ex[qj[t]] = (float)rx[t] * (1.0f / 4096.0f);
+            a.dbg_ey[qj[t]] = (float)ry[t] * (1.0f / 4096.0f);
+        }
+    }
+    return part;
+}
+
 template <int K>
 __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *buf, long long *s_part,
                            int32_t *s_red)
@@ -749,10 +928,12 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *bu
     const int tid = threadIdx.x;
     long long part = 0;
     if (m > K) {
-        if (m - q0 <= kBlock)
-            part = split_body<K, 1>(a, w, d, ax, q0, buf);
+        if (ax.nb)
+            part = split_body_sorted<K>(a, w, d, ax, q0, buf);
+        else if (m - q0 <= kBlock)
+            part = split_body_wide<K, 1>(a, w, d, ax, q0, buf);
         else
-            part = split_body<K, 2>(a, w, d, ax, q0, buf);
+            part = split_body_wide<K, 2>(a, w, d, ax, q0, buf);
     }
     // workgroup sum of the fixed-point terms (exact, order-free)
     for (int o = 32; o > 0; o >>= 1)
@@ -1156,7 +1337,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
             // a sort that split items of the window will wait for: its waves
             // issue ahead of theirs
             __builtin_amdgcn_s_setprio(3);
-            prep_item(a, itm.win, buf);
+            prep_item(a, itm.win, buf, s_red);
             __builtin_amdgcn_s_setprio(0);
         } else {
             // split items are the largest, taken first: let their waves issue
@@ -1222,9 +1403,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LaunchArgs a, const Part
 __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint32_t buf[kMaxWindow];
+    __shared__ int32_t s_red[5];
     const uint32_t pi = a.win_begin + blockIdx.x;
     if (pi < a.n_prep)
-        prep_item(a, a.prep_list[pi], buf);
+        prep_item(a, a.prep_list[pi], buf, s_red);
 }
 
 // --------------------------------------------------------------------------

@@ -136,10 +136,11 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
 }
 
 // Batched form: the queue the persistent kernel takes items from.  Prep
-// items (one per split window, largest first) come first; then the other
-// items, largest cost first (a stable bucket order by log2(cost) is enough
-// for the greedy schedule).  Split items wait for their window's prep item
-// only before their counting phase.
+// items (one per split window, largest first) come first, then the local
+// items, then the split items, each class largest cost first (a stable bucket
+// order by log2(cost) is enough for the greedy schedule).  A split item scans
+// its window in x order, which its prep item writes: the local items in
+// between keep the device busy while those sorts finish.
 inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vector<Item> &queue)
 {
     queue.clear();
@@ -148,16 +149,22 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
     std::stable_sort(prep.begin(), prep.end(), [&](uint32_t a, uint32_t b) { return wm[a] > wm[b]; });
     for (uint32_t w : prep)
         queue.push_back(Item{w, kItemPrep});
-    std::vector<uint32_t> cnt(66, 0);
     auto bucket = [](uint64_t c) { return 63 - (63 - __builtin_clzll(c | 1ull)); };
-    for (uint64_t c : P.cost)
-        cnt[bucket(c) + 1]++;
-    for (int i = 1; i <= 65; ++i)
-        cnt[i] += cnt[i - 1];
-    const size_t base = queue.size();
-    queue.resize(base + P.items.size());
-    for (size_t i = 0; i < P.items.size(); ++i)
-        queue[base + cnt[bucket(P.cost[i])]++] = P.items[i];
+    for (int local = 1; local >= 0; --local) {
+        std::vector<uint32_t> cnt(66, 0);
+        std::vector<size_t> idx;
+        for (size_t i = 0; i < P.items.size(); ++i)
+            if (((P.items[i].info & kItemLocal) != 0) == (local == 1)) {
+                cnt[bucket(P.cost[i]) + 1]++;
+                idx.push_back(i);
+            }
+        for (int i = 1; i <= 65; ++i)
+            cnt[i] += cnt[i - 1];
+        const size_t base = queue.size();
+        queue.resize(base + idx.size());
+        for (size_t i : idx)
+            queue[base + cnt[bucket(P.cost[i])]++] = P.items[i];
+    }
 }
 
 // Serving: local windows per item for a run of windows of m points (the
@@ -170,9 +177,9 @@ inline uint32_t plan_local_per_item(uint32_t m)
 }
 
 // Serving: queue layout of a launch made of parts (m and count set, in launch
-// window order).  Sets win0, and per part its prep items, sorted-marginal
-// offset and items: all prep items first, then split items, then local
-// items, larger windows first within each.  Returns the queue length; *split
+// window order).  Sets win0, and per part its prep items, sorted-data offset
+// and items: all prep items first, then local items, then split items,
+// larger windows first within each.  Returns the queue length; *split
 // receives the sorted-marginal points (sum of m over split windows).
 inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split)
 {
@@ -196,15 +203,15 @@ inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split)
             sorted += (uint64_t)pd[i].count * pd[i].m;
         }
     for (uint32_t i : order)
-        if (pd[i].m > (uint32_t)kLocalSlots) {
-            pd[i].item0 = q;
-            q += pd[i].count * ((pd[i].m + kSplitPoints - 1) / kSplitPoints);
-        }
-    for (uint32_t i : order)
         if (pd[i].m <= (uint32_t)kLocalSlots) {
             pd[i].item0 = q;
             pd[i].per_item = plan_local_per_item(pd[i].m);
             q += (pd[i].count + pd[i].per_item - 1) / pd[i].per_item;
+        }
+    for (uint32_t i : order)
+        if (pd[i].m > (uint32_t)kLocalSlots) {
+            pd[i].item0 = q;
+            q += pd[i].count * ((pd[i].m + kSplitPoints - 1) / kSplitPoints);
         }
     *split = sorted;
     return q;

@@ -644,7 +644,7 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     size_t o_prep = align_up(o_qd + count * sizeof(QDesc), A);
     size_t desc_bytes = align_up(o_prep + n_prep * sizeof(uint32_t), A);
     size_t o_sorted = desc_bytes;
-    size_t o_acc = align_up(o_sorted + 2 * split_pts * sizeof(int32_t), A);
+    size_t o_acc = align_up(o_sorted + (size_t)kSortedWords * split_pts * sizeof(int32_t), A);
     size_t o_wdone = align_up(o_acc + n_win * sizeof(unsigned long long), A);
     size_t o_qdone = align_up(o_wdone + n_win * sizeof(uint32_t), A);
     size_t o_counter = align_up(o_qdone + count * sizeof(uint32_t), A);

@@ -164,7 +164,7 @@ void layout_slot(Slot &s, uint32_t cap_windows, uint32_t cap_items, uint64_t cap
     s.o_queue = align_up(s.o_qd + (size_t)cap_windows * sizeof(QDesc), A);
     s.o_cdst = align_up(s.o_queue + (size_t)cap_items * sizeof(Item), A);
     s.o_sorted = align_up(s.o_cdst + (size_t)cap_windows * sizeof(uint64_t), A);
-    s.o_acc = align_up(s.o_sorted + 2 * cap_split * sizeof(int32_t), A);
+    s.o_acc = align_up(s.o_sorted + (size_t)kSortedWords * cap_split * sizeof(int32_t), A);
     s.o_wdone = align_up(s.o_acc + (size_t)cap_windows * sizeof(unsigned long long), A);
     s.o_qdone = align_up(s.o_wdone + (size_t)cap_windows * sizeof(uint32_t), A);
     s.o_counter = align_up(s.o_qdone + (size_t)cap_windows * sizeof(uint32_t), A);

@@ -170,8 +170,8 @@ static int check_parts(std::vector<PartDesc> pd)
     std::vector<int> queue(n_items, 0);  // 1 prep, 2 split, 3 local
     std::vector<int> covered(n_win, 0), prepped(n_win, 0);
     std::vector<char> sorted_used(split, 0);
-    uint32_t last_prep = 0, first_split = n_items, last_split = 0, first_local = n_items;
-    bool any_prep = false, any_split = false;
+    uint32_t last_prep = 0, first_split = n_items, last_local = 0;
+    bool any_prep = false, any_local = false;
     for (const PartDesc &p : pd) {
         const bool big = p.m > (uint32_t)kLocalSlots;
         const uint32_t nsplit = (p.m + kSplitPoints - 1) / kSplitPoints;
@@ -195,8 +195,6 @@ static int check_parts(std::vector<PartDesc> pd)
                     if (qs >= n_items || queue[qs]++)
                         return fail("split entry", (long)qs, (long)n_items);
                     first_split = std::min(first_split, qs);
-                    last_split = std::max(last_split, qs);
-                    any_split = true;
                 }
                 covered[w]++;
             } else if (i % p.per_item == 0) {
@@ -204,7 +202,8 @@ static int check_parts(std::vector<PartDesc> pd)
                 const uint32_t ql = p.item0 + i / p.per_item;
                 if (ql >= n_items || queue[ql]++)
                     return fail("local entry", (long)ql, (long)n_items);
-                first_local = std::min(first_local, ql);
+                last_local = std::max(last_local, ql);
+                any_local = true;
                 if (nw > (uint32_t)kLocalWindows || nw * ((p.m + 1u) & ~1u) > (uint32_t)kLocalSlots ||
                     nw * plan_pow2(std::max(p.m, 2u)) > (uint32_t)kLocalSort)
                     return fail("local item limits", (long)p.m, (long)nw);
@@ -222,8 +221,14 @@ static int check_parts(std::vector<PartDesc> pd)
     for (size_t j = 0; j < split; ++j)
         if (sorted_used[j] != 1)
             return fail("sorted point unused", (long)j, 0);
-    if ((any_prep && any_split && last_prep >= first_split) || (any_split && last_split >= first_local))
-        return fail("queue order prep < split < local", (long)last_prep, (long)first_local);
+    if ((any_prep && last_prep >= first_split) || (any_local && last_local >= first_split))
+        return fail("queue order: prep and local items before split items", (long)last_prep, (long)first_split);
+    if (any_prep && any_local) {
+        // every prep item precedes every local item
+        for (const PartDesc &p : pd)
+            if (p.m <= (uint32_t)kLocalSlots && p.count && p.item0 <= last_prep)
+                return fail("local item before a prep item", (long)p.item0, (long)last_prep);
+    }
     return 0;
 }
 
