@@ -218,6 +218,7 @@ def chunked_bench(wmi, torch, w, steps: int) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     main_ms = float(sum(b.timing()["main_ms"] for b in batches))
+    evaluated = int(sum(b.count_evals() for b in batches))  # untimed extra pass with counters
     for b in batches:
         b.destroy()
     st.close()
@@ -228,6 +229,8 @@ def chunked_bench(wmi, torch, w, steps: int) -> dict:
             "distance_ops_frac_valu_peak": pairs * OPS_PER_PAIR / dt / 1e12 / VALU_PEAK_TOPS,
             "main_kernel_ms_sum": main_ms,
             "main_kernel_frac_valu_peak": pairs * OPS_PER_PAIR / (main_ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+            "evaluated_pairs": evaluated,
+            "main_kernel_evaluated_frac": evaluated * OPS_PER_PAIR / (main_ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
             "first_submit_s": t_submit}
 
 
@@ -355,6 +358,10 @@ def main():
     again = b.read()
     assert np.array_equal(first.view(np.uint8), again.view(np.uint8)), "replay changed results"
     log(f"direct: {ms_step:.3f} ms/step, main kernel {tim['main_ms']:.3f} ms, prep {tim['prep_ms']:.3f} ms")
+    # distances the kernel computes (an extra, untimed run with counters):
+    # split windows scan outwards in x order and stop early
+    evaluated = b.count_evals()
+    log(f"distance evaluations per launch: {evaluated} ({evaluated / pairs:.3f} of the ordered pairs)")
 
     # ---- the same steps as graph launches -----------------------------------
     b.replay()
@@ -435,7 +442,9 @@ def main():
                      "traffic": (TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
                                  if kernel_source_hash() == TRAFFIC["kernel_sha256"] else None),
                      "traffic_unit": "HBM bytes per launch (fetch + write, calibrated counters)",
-                     "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs},
+                     "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs,
+                     "evaluated_pairs_per_launch": evaluated,
+                     "evaluated_frac": evaluated * OPS_PER_PAIR / (tim["main_ms"] / 1e3) / 1e12 / VALU_PEAK_TOPS},
         "plain_gpu": plain,
     }
     if not args.no_serve:

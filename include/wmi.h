@@ -218,6 +218,19 @@ int wmi_batch_timing(wmi_batch *batch, wmi_timing *out);
 /* Counters and device time of a finished batch (of its last run). */
 int wmi_batch_stats_get(wmi_batch *batch, wmi_batch_stats *out);
 
+/*
+ * Distance evaluations of the batch's main kernel: runs the batch's kernels
+ * once more (results are rewritten with the same values) with a per-workgroup
+ * counter and writes to *evaluated the number of (query point, candidate)
+ * distances the neighbour searches computed for live query points, the point
+ * itself excluded.  The estimator's definition (Eq. 2) asks for the k nearest
+ * of all m - 1 other points, so m (m - 1) per window is the brute-force count;
+ * split windows scan outwards in x order and stop early, so the count is
+ * lower there.  Synchronous on the batch's stream; allocates 8 bytes per
+ * main-kernel workgroup for the call.  WMI_EINVAL for plain batches.
+ */
+int wmi_batch_count_evals(wmi_batch *batch, uint64_t *evaluated);
+
 /* Wait for the batch and release it (NULL is accepted). */
 int wmi_batch_destroy(wmi_batch *batch);
 

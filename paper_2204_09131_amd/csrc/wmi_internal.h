@@ -139,6 +139,8 @@ struct LaunchArgs {
     // debug export (one window): per point counts and radii, or null
     uint32_t *dbg_nx, *dbg_ny;
     float *dbg_ex, *dbg_ey;
+    // distance evaluations per workgroup (one counter per workgroup), or null
+    unsigned long long *evals;
 };
 
 }  // namespace wmi

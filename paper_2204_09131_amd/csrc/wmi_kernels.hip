@@ -80,6 +80,15 @@ __device__ __forceinline__ void block_sync()
     __syncthreads();
 }
 
+// Add a wave's distance evaluations, n_live query points times `per_query`
+// candidates each, to its workgroup's counter (only when counting).  Every
+// lane of the wave calls it with the same values.
+__device__ __forceinline__ void count_evals(const LaunchArgs &a, int n_live, int per_query)
+{
+    if (a.evals && (threadIdx.x & 63) == 0 && n_live > 0 && per_query > 0)
+        atomicAdd(&a.evals[blockIdx.x], (unsigned long long)n_live * (unsigned long long)per_query);
+}
+
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T>
@@ -633,6 +642,13 @@ __device__ __forceinline__ long long split_body_wide(const LaunchArgs &a, uint32
         block_sync();
         scan_wide<K, Q>(buf, c0, cn, qx, qy, top);
     }
+    {
+        int n_live = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            n_live += __popcll(__ballot(q0 + tid + q * kBlock < m));
+        count_evals(a, n_live, m - 1);
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
         split_radii<K, unsigned long long>(top[q], (unsigned long long)min(q0 + tid + q * kBlock, m - 1), 12,
@@ -824,6 +840,7 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
         const int w_lo = __builtin_amdgcn_readfirstlane(q0 + 128 * wave);
         if (w_lo < m) {
             const int w_hi = min(m, w_lo + 128);
+            int scanned = w_hi - w_lo;
             stage_wave(wb, KX, YS, w_lo, w_hi - w_lo, mask);
             scan_wave<K, true>(wb, w_hi - w_lo, qx, qy, qj, top);
             uint32_t dist[2];
@@ -844,6 +861,7 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
                     scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
                     const uint32_t e = wb[cnt - 1].x;
                     r += cnt;
+                    scanned += cnt;
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
                         dist[t] = e - qx[t];
@@ -855,12 +873,15 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
                     scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
                     const uint32_t e = wb[0].x;
                     l -= cnt;
+                    scanned += cnt;
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
                         dist[t] = qx[t] - e;
                     lopen = l > 0 && side_open<K>(live, dist, top, mask);
                 }
             }
+            const int n_live = __popcll(__ballot(live[0])) + __popcll(__ballot(live[1]));
+            count_evals(a, n_live, scanned - 1);  // the own point is masked, not evaluated
         }
     }
     uint32_t rx[2], ry[2];
@@ -1235,6 +1256,8 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             const int mode = __builtin_amdgcn_readfirstlane(
                 nb_min == 0u ? 3 : (w_min == w_max ? 0 : (m_max == m_min ? 1 : 2)));
             local_knn2<K>(cand, L.off[wl], m, il, nb, mode, m_max, band0, a.estimator, RX, RY);
+            const int n_live = __popcll(__ballot(live)) + __popcll(__ballot(live && act[1]));
+            count_evals(a, n_live, m_max - 1);
         }
     }
     block_sync();

@@ -898,6 +898,60 @@ int wmi_batch_stats_get(wmi_batch *b, wmi_batch_stats *out)
     return WMI_OK;
 }
 
+int wmi_batch_count_evals(wmi_batch *b, uint64_t *evaluated)
+{
+    if (!b || !evaluated)
+        return fail(WMI_EINVAL, "wmi_batch_count_evals: null argument");
+    if (b->params.flags & WMI_SUBMIT_PLAIN)
+        return fail(WMI_EINVAL, "wmi_batch_count_evals: not available for plain batches");
+    wmi_store *st = b->st;
+    DeviceGuard g(st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    *evaluated = 0;
+    if (!b->count || !b->grid)
+        return WMI_OK;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        for (uint32_t id : b->series_used)
+            if (id >= st->series.size() || !st->series[id].live)
+                return fail(WMI_ESTATE, "series %u of the batch was removed", id);
+        hold_locked(b);
+    }
+    auto release = [&]() {
+        std::lock_guard<std::mutex> lk(st->mu);
+        release_locked(b);
+    };
+    unsigned long long *cnt = nullptr;
+    hipError_t e = hipMalloc(&cnt, sizeof(unsigned long long) * b->grid);
+    if (e != hipSuccess) {
+        release();
+        return fail(WMI_EHIP, "wmi_batch_count_evals: hipMalloc of %u counters failed", b->grid);
+    }
+    LaunchArgs a = b->args;
+    a.evals = cnt;
+    hipStream_t s = b->stream;
+    std::vector<unsigned long long> h(b->grid);
+    uint32_t err = 0;
+    if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * b->grid, s)) == hipSuccess &&
+        (e = launch_clear(a, s)) == hipSuccess && (e = launch_main(a, b->grid, s)) == hipSuccess &&
+        (e = hipMemcpyAsync(h.data(), cnt, sizeof(unsigned long long) * b->grid, hipMemcpyDeviceToHost, s)) ==
+            hipSuccess &&
+        (e = hipMemcpyAsync(&err, a.err, sizeof err, hipMemcpyDeviceToHost, s)) == hipSuccess)
+        e = hipStreamSynchronize(s);
+    (void)hipFree(cnt);
+    release();
+    if (e != hipSuccess)
+        return poison(st, e, "wmi_batch_count_evals");
+    if (err)
+        return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
+    uint64_t total = 0;
+    for (unsigned long long v : h)
+        total += v;
+    *evaluated = total;
+    return WMI_OK;
+}
+
 int wmi_batch_destroy(wmi_batch *b)
 {
     if (!b)

@@ -50,7 +50,7 @@ WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("m
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
            "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
-           "wmi_batch_stats_get", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
+           "wmi_batch_stats_get", "wmi_batch_count_evals", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
            "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
            "wmi_td_search", "wmi_bu_search")
@@ -154,6 +154,7 @@ def lib():
         "wmi_batch_replay": ([vp, vp, u32], ctypes.c_int),
         "wmi_batch_timing": ([vp, P(_Timing)], ctypes.c_int),
         "wmi_batch_stats_get": ([vp, P(_Stats)], ctypes.c_int),
+        "wmi_batch_count_evals": ([vp, P(ctypes.c_uint64)], ctypes.c_int),
         "wmi_batch_destroy": ([vp], ctypes.c_int),
         "wmi_debug_window": ([vp, vp, P(_Params), vp, vp, vp, vp], ctypes.c_int),
         "wmi_psi_table": ([u32, vp], ctypes.c_int),
@@ -247,6 +248,13 @@ class Batch:
         return {"windows": s.windows, "ordered_pairs": s.ordered_pairs, "launches": s.launches,
                 "device_ms": s.device_ms, "items": s.items, "grid": s.grid, "wg_per_cu": s.wg_per_cu,
                 "cus": s.cus}
+
+    def count_evals(self) -> int:
+        """(query point, candidate) distances the neighbour searches compute
+        (one extra run of the kernels; synchronous)."""
+        n = ctypes.c_uint64(0)
+        _check(lib().wmi_batch_count_evals(self.h, ctypes.byref(n)))
+        return n.value
 
     def destroy(self):
         if self.h:

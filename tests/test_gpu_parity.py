@@ -269,6 +269,48 @@ def test_tau_normalize(store, orc):
     store.remove_series(b)
 
 
+def test_count_evals(store, cfg1, orc):
+    """The evaluation counter: m (m - 1) per window where nothing can be
+    skipped, fewer for split windows whose x order lets the scan stop; the
+    counting run rewrites the same results."""
+    w, q = cfg1
+    b = store.submit(q, k=4)
+    first = b.read().copy()
+    m = q["len"].astype(np.int64)
+    assert b.count_evals() == int(np.sum(m * (m - 1)))  # one window length: local items scan m - 1 each
+    assert b.read().tobytes() == first.tobytes()
+    b.destroy()
+    # constant x: every |dx| is 0, no side of an outward scan can close
+    n = 4096
+    _, y = synth.bivariate_normal(n, 0.0, 21)
+    a_id = store.add_series(np.zeros(n, np.float32))
+    b_id = store.add_series(y)
+    try:
+        for m_ in (513, 1000, 4096):
+            qq = synth.make_queries(a_id, b_id, 0, m_)
+            bb = store.submit(qq, k=4)
+            res = bb.read().copy()
+            assert bb.count_evals() == m_ * (m_ - 1), m_
+            ref = orc.batch([np.zeros(n, np.float32), y], synth.make_queries(0, 1, 0, m_), k=4)
+            mi_close(res, ref, ("mi_base",))
+            bb.destroy()
+    finally:
+        store.remove_series(a_id)
+        store.remove_series(b_id)
+    # independent normal data at m = 4096: the scan stops well short of all pairs
+    x, y = synth.bivariate_normal(n, 0.0, 22)
+    a_id, b_id = store.add_series(x), store.add_series(y)
+    try:
+        bb = store.submit(synth.make_queries(a_id, b_id, 0, n), k=4)
+        ev = bb.count_evals()
+        log(f"m = {n}: {ev} of {n * (n - 1)} pairs evaluated ({ev / (n * (n - 1)):.3f})")
+        assert n * 127 <= ev < n * (n - 1)
+        bb.destroy()
+    finally:
+        store.remove_series(a_id)
+        store.remove_series(b_id)
+
+
 def test_offgrid_flag_and_device_series(store, orc):
     import torch
     x, y = synth.relation("linear", 500, 8)
