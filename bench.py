@@ -46,8 +46,8 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # same counter reads for an elementwise kernel of known traffic (256 MiB read,
 # 256 MiB written): FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0.  Valid only for the
 # kernel source it was taken on (hash of the kernel and descriptor sources).
-TRAFFIC = {"kernel_sha256": "6cd24fc042cfe4917dc454b08f287b64555bb54beeda052d421a4307966fc749",
-           "fetch_bytes": 46027530, "write_bytes": 14401088}
+TRAFFIC = {"kernel_sha256": "686e33a92f82019f477f1b703b87566c2dcb3ea412fbaa11176c894f55988bb4",
+           "fetch_bytes": 68068589, "write_bytes": 31237734}
 
 
 def kernel_source_hash() -> str:
