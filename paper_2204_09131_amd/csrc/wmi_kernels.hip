@@ -807,6 +807,52 @@ __device__ __forceinline__ uint64_t key_below(int64_t v, uint32_t nb)
     return (uint64_t)v << nb;
 }
 
+// A wave stops its shared scan once at most this many of its query slots can
+// still gain from a side; those finish one at a time with the whole wave.
+constexpr int kStragglers = 4;
+
+// One straggler's scan of one side, by the whole wave: candidates from `edge`
+// outwards (RIGHT: edge, edge + 1, ...; left: edge - 1, edge - 2, ...), 256
+// a round, one per lane per group of 64, into per-lane k-lists.  `bound` is
+// the query's current k-th key with the index bits set: a candidate whose x
+// distance exceeds it cannot enter, nor can any further out, so the side ends
+// after the round whose outermost candidate is past it.  Returns the
+// candidates evaluated.
+template <int K, bool RIGHT>
+__device__ __forceinline__ int straggler_side(const uint32_t *__restrict__ KX, const uint32_t *__restrict__ YS,
+                                              int edge, int m, uint32_t sx, uint32_t sy, uint32_t bound,
+                                              uint32_t mask, uint32_t (&pt)[K])
+{
+    const int lane = threadIdx.x & 63;
+    const int avail = RIGHT ? m - edge : edge;  // candidates on this side
+    int done = 0;
+    while (done < avail) {
+        const int n = min(256, avail - done);
+        uint32_t kx[4], ky[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int off = done + 64 * g + lane;
+            const int o = min(off, done + n - 1);  // past the end: repeat the round's last candidate
+            const int p = RIGHT ? edge + o : edge - 1 - o;
+            kx[g] = KX[p];
+            ky[g] = YS[p];
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t cx = kx[g] & ~mask, cj = kx[g] & mask;
+            uint32_t key = tmax(sad_key_v(sx, cx, cj), sad_key_v(sy, ky[g], cj));
+            key = 64 * g + lane < n ? key : 0xFFFFFFFFu;
+            insert_sorted<K>(pt, key);
+        }
+        done += n;
+        const int pf = RIGHT ? edge + done - 1 : edge - done;  // the outermost candidate so far
+        const uint32_t fx = (uint32_t)__builtin_amdgcn_readfirstlane((int)(KX[pf] & ~mask));
+        if ((RIGHT ? fx - sx : sx - fx) > bound)
+            break;
+    }
+    return min(done, avail);
+}
+
 template <int K>
 __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const WinDesc &d, const WinAux &ax, int q0,
                                        uint32_t *buf)
@@ -836,52 +882,99 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
     // ---- neighbours, wave by wave
     {
         const int wave = tid >> 6;
+        const int lane = tid & 63;
         uint4 *wb = reinterpret_cast<uint4 *>(buf) + wave * kWaveChunk;
         const int w_lo = __builtin_amdgcn_readfirstlane(q0 + 128 * wave);
         if (w_lo < m) {
             const int w_hi = min(m, w_lo + 128);
-            int scanned = w_hi - w_lo;
             stage_wave(wb, KX, YS, w_lo, w_hi - w_lo, mask);
             scan_wave<K, true>(wb, w_hi - w_lo, qx, qy, qj, top);
-            uint32_t dist[2];
-            const uint32_t redge = wb[w_hi - w_lo - 1].x, ledge = wb[0].x;
+            int scanned = w_hi - w_lo;
+            // x keys of the outermost candidates scanned on each side
+            uint32_t er = wb[w_hi - w_lo - 1].x, el = wb[0].x;
             int r = w_hi, l = w_lo;
+            bool nr[2], nl[2];
+            for (;;) {
+                // which queries can still gain from each side
+                int needy = 0;
+                bool any_r = false, any_l = false;
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-                dist[t] = redge - qx[t];
-            bool ropen = r < m && side_open<K>(live, dist, top, mask);
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-                dist[t] = qx[t] - ledge;
-            bool lopen = l > 0 && side_open<K>(live, dist, top, mask);
-            while (ropen || lopen) {
-                if (ropen) {
+                for (int t = 0; t < 2; ++t) {
+                    const uint32_t lim = top[t][K - 1] | mask;
+                    nr[t] = live[t] && r < m && er - qx[t] <= lim;
+                    nl[t] = live[t] && l > 0 && qx[t] - el <= lim;
+                    needy += __popcll(__ballot(nr[t] || nl[t]));
+                    any_r = any_r || __ballot(nr[t]) != 0ull;
+                    any_l = any_l || __ballot(nl[t]) != 0ull;
+                }
+                // a few queries still open: they finish alone below
+                if (needy <= kStragglers)
+                    break;
+                if (any_r) {
                     const int cnt = min(kWaveChunk, m - r);
                     stage_wave(wb, KX, YS, r, cnt, mask);
                     scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
-                    const uint32_t e = wb[cnt - 1].x;
+                    er = wb[cnt - 1].x;
                     r += cnt;
                     scanned += cnt;
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        dist[t] = e - qx[t];
-                    ropen = r < m && side_open<K>(live, dist, top, mask);
                 }
-                if (lopen) {
+                if (any_l) {
                     const int cnt = min(kWaveChunk, l);
                     stage_wave(wb, KX, YS, l - cnt, cnt, mask);
                     scan_wave<K, false>(wb, cnt, qx, qy, qj, top);
-                    const uint32_t e = wb[0].x;
+                    el = wb[0].x;
                     l -= cnt;
                     scanned += cnt;
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        dist[t] = qx[t] - e;
-                    lopen = l > 0 && side_open<K>(live, dist, top, mask);
                 }
             }
             const int n_live = __popcll(__ballot(live[0])) + __popcll(__ballot(live[1]));
             count_evals(a, n_live, scanned - 1);  // the own point is masked, not evaluated
+            // stragglers, one at a time: the whole wave scans the sides the
+            // query still needs, then merges the lanes' lists into its own
+            unsigned long long s0 = __ballot(nr[0] || nl[0]), s1 = __ballot(nr[1] || nl[1]);
+            while ((s0 | s1) != 0ull) {
+                const int t = s0 != 0ull ? 0 : 1;
+                const int L = __ffsll((long long)(t == 0 ? s0 : s1)) - 1;
+                if (t == 0)
+                    s0 &= s0 - 1ull;
+                else
+                    s1 &= s1 - 1ull;
+                const uint32_t sx = __builtin_amdgcn_readlane(t == 0 ? qx[0] : qx[1], L);
+                const uint32_t sy = __builtin_amdgcn_readlane(t == 0 ? qy[0] : qy[1], L);
+                const uint32_t bound =
+                    __builtin_amdgcn_readlane(t == 0 ? top[0][K - 1] : top[1][K - 1], L) | mask;
+                const int need_r = __builtin_amdgcn_readlane((int)(t == 0 ? nr[0] : nr[1]), L);
+                const int need_l = __builtin_amdgcn_readlane((int)(t == 0 ? nl[0] : nl[1]), L);
+                uint32_t pt[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q)
+                    pt[q] = 0xFFFFFFFFu;
+                int cand = 0;
+                if (need_r)
+                    cand += straggler_side<K, true>(KX, YS, r, m, sx, sy, bound, mask, pt);
+                if (need_l)
+                    cand += straggler_side<K, false>(KX, YS, l, m, sx, sy, bound, mask, pt);
+                // after the butterfly every lane holds the k smallest of all lists
+                for (int o = 32; o > 0; o >>= 1) {
+                    uint32_t other[K];
+#pragma unroll
+                    for (int q = 0; q < K; ++q)
+                        other[q] = (uint32_t)__shfl_xor((int)pt[q], o, 64);
+#pragma unroll
+                    for (int q = 0; q < K; ++q)
+                        insert_sorted<K>(pt, other[q]);
+                }
+                if (lane == L) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) {
+                        if (t == 0)
+                            insert_sorted<K>(top[0], pt[q]);
+                        else
+                            insert_sorted<K>(top[1], pt[q]);
+                    }
+                }
+                count_evals(a, 1, cand);
+            }
         }
     }
     uint32_t rx[2], ry[2];
