@@ -9,35 +9,41 @@
 // Section 7.1.1: counts use <= and include the neighbours, not the point).
 //
 // No MFMA anywhere: a max-norm neighbour search is not a contraction; the
-// bound is the 32-bit VALU.  Work comes in two kinds of items, taken
-// largest first from an atomic counter by a persistent kernel:
+// bound is the 32-bit VALU.  A persistent kernel takes items from an atomic
+// counter; the queue holds prep items, then local items, then split items:
 //
 //   local item  up to 16 consecutive windows of at most 512 points in total
 //               (whole queries, noise triples included, where they fit).
 //               One workgroup stages them in LDS, finds every point's
-//               neighbours, sorts each window's marginals in LDS (bitonic),
-//               counts by binary search, sums digamma terms with LDS integer
-//               atomics and writes the results: no global atomics, no fences.
-//   split item  512 query points of a window above 512 points.  A prep
-//               item at the head of the same queue sorts the window's
-//               marginals into HBM (the plain form launches a prep kernel
-//               instead); a split item finds its neighbours first and waits
-//               (bounded) for that sort only before counting.  Items add
+//               neighbours (all pairs), sorts each window's marginals in LDS
+//               (bitonic), counts by binary search, sums digamma terms with
+//               LDS integer atomics and writes the results: no global
+//               atomics, no fences.
+//   prep item   one window above 512 points: its x order as keys carrying
+//               the point index with the y key of each point beside it, and
+//               the sorted y integers, written to HBM before the window's
+//               ready flag (the plain form launches a prep kernel instead).
+//   split item  512 consecutive positions of such a window's x order.  Each
+//               wave scans candidates outward from its 128 queries in x
+//               order, stops once few queries can still gain, and finishes
+//               those one at a time with the whole wave; then the item
+//               counts by binary search over the sorted data.  Items add
 //               exact fixed-point digamma sums with integer atomics and the
 //               last item of a window forms its estimate.
 //
-// Neighbour search.  Each lane owns query points and scans all m candidates
-// of its window from LDS, keeping the k+1 smallest 32-bit keys in registers
-// with a branch-free med3 insertion network; the point itself is dropped at
-// the end.  With grid integers X = v * 2^12 and U = (X - min) << nb,
-// 2^nb >= m, the key of candidate j is
+// Keys.  With grid integers X = v * 2^12 and U = (X - min) << nb, 2^nb >= m,
+// the key of candidate j for query i is
 //   max(|Ux_i - Ux_j| + j, |Uy_i - Uy_j| + j) = (d_ij << nb) | j,
 // so unsigned order is the order of (distance, index): ties go to the earlier
-// time index.  Two v_sad_u32 and one v_max_u32 build a key.  A window whose
-// value range does not fit 32 - nb bits uses 64-bit keys (d << 12 | j).
+// time index.  Two v_sad_u32 and one v_max_u32 build a key, and the k (or
+// k+1, the point itself dropped at the end) smallest stay in registers under
+// a branch-free med3 insertion network.  A window whose value range does not
+// fit 32 - nb bits uses 64-bit keys (d << 12 | j) and scans all candidates.
 //
-// Cross-workgroup results travel only through returning atomics issued in
-// order (an s_waitcnt between them); no cache write-back fences are used.
+// Cross-workgroup values: sums, counters and estimates travel through
+// returning atomics issued in order (an s_waitcnt between them); a split
+// window's sorted data is published by a device-scope release fence before
+// its ready flag and read after an acquire fence.
 #include <hip/hip_runtime.h>
 
 #include "wmi_internal.h"
