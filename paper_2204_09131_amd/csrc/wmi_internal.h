@@ -75,6 +75,7 @@ struct WinAux {             // per split item, computed by the item itself
     int32_t min_x, min_y;   // window minima of the grid integers
     uint32_t nb;            // index bits in a 32-bit key; 0 selects 64-bit keys
     uint32_t flags;         // kFlagOffGrid
+    uint32_t range_x, range_y;  // max - min of the grid integers
 };
 
 struct Result {             // 32 bytes, same layout as wmi_result

@@ -278,60 +278,120 @@ __device__ void bitonic_lds(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
     block_sync();
 }
 
-// Sort the grid integers of one coordinate of a window into out[0..m)
-// (P = next power of two >= m entries of scratch, P <= kMaxWindow).
-__device__ void sort_marginal(const float *v, int m, int32_t *scratch, int32_t *out)
+__device__ WinAux window_aux(const WinDesc &d, int32_t *s_red);
+
+// Stable LSD radix sort of the n <= kMaxWindow words a[0, n) in LDS on bits
+// [lo, lo + 4 passes), 4 bits a pass; bits below lo keep their order (the
+// sort is stable), bits above are zero.  Wave w holds positions
+// [w 64 E, (w + 1) 64 E) striped, element e of lane l at w 64 E + 64 e + l,
+// so ranking lanes in order round by round is ranking positions in order.  A
+// key's rank among equal digits of its wave comes from four ballots; the
+// wave's running digit counts sit in lanes 0..15; one wave scans the 16 x 4
+// digit-major totals in s_cnt.  Keys stay in registers across the pass, so
+// the scatter writes back into a[] itself.  Positions past n sort last
+// (all-ones digits, stable) and are never stored.
+__device__ __forceinline__ void radix_lds(uint32_t *a, int n, int lo, int passes, uint32_t *s_cnt)
 {
-    const int tid = threadIdx.x;
-    int P = 1;
-    while (P < m)
-        P <<= 1;
-    uint32_t off = 0;
-    block_sync();
-    for (int i = tid; i < P; i += kBlock)
-        scratch[i] = i < m ? grid_int(v[i], off) : INT32_MAX;
-    bitonic_lds<kMaxWindow / (2 * kBlock), 1>(scratch, nullptr, (uint32_t)P, (uint32_t)P);
-    for (int i = tid; i < m; i += kBlock)
-        out[i] = scratch[i];
+    constexpr int EM = kMaxWindow / kBlock;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int E = (n + kBlock - 1) / kBlock;
+    const int wbase = wave * 64 * E;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const uint32_t dl = (uint32_t)lane & 15u;
+    for (int p = 0; p < passes; ++p) {
+        const int sh = lo + 4 * p;
+        uint32_t key[EM], rk[EM];
+        block_sync();  // the previous pass's scatter is complete
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            const int pos = wbase + 64 * e + lane;
+            key[e] = (e < E && pos < n) ? a[pos] : 0xFFFFFFFFu;
+        }
+        uint32_t cnt = 0;  // lane d < 16: keys of digit d met so far in this wave
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            if (e < E) {
+                // one round at a time: tie this round's digit to the last
+                // round's count, so rounds are not interleaved (their ballots
+                // would all be live at once)
+                uint32_t kk = key[e];
+                asm volatile("" : "+v"(kk) : "v"(cnt));
+                const uint32_t dg = (kk >> sh) & 15u;
+                const unsigned long long b0 = __ballot(dg & 1u), b1 = __ballot(dg & 2u);
+                const unsigned long long b2 = __ballot(dg & 4u), b3 = __ballot(dg & 8u);
+                const unsigned long long same = ((dg & 1u) ? b0 : ~b0) & ((dg & 2u) ? b1 : ~b1) &
+                                                ((dg & 4u) ? b2 : ~b2) & ((dg & 8u) ? b3 : ~b3);
+                rk[e] = (uint32_t)__shfl((int)cnt, (int)dg, 64) + (uint32_t)__popcll(same & lt);
+                const unsigned long long mine = ((dl & 1u) ? b0 : ~b0) & ((dl & 2u) ? b1 : ~b1) &
+                                                ((dl & 4u) ? b2 : ~b2) & ((dl & 8u) ? b3 : ~b3);
+                cnt += (uint32_t)__popcll(mine);
+            }
+        }
+        if (lane < 16)
+            s_cnt[lane * 4 + wave] = cnt;
+        block_sync();  // every wave has read its keys and published its counts
+        if (wave == 0) {
+            const uint32_t v = s_cnt[lane];
+            uint32_t incl = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+                if (lane >= o)
+                    incl += u;
+            }
+            s_cnt[lane] = incl - v;
+        }
+        block_sync();
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            if (e < E) {
+                const uint32_t dg = (key[e] >> sh) & 15u;
+                const uint32_t t = s_cnt[dg * 4 + wave] + rk[e];
+                if (t < (uint32_t)n)
+                    a[t] = key[e];
+            }
+        }
+    }
     block_sync();
 }
 
-__device__ WinAux window_aux(const WinDesc &d, int32_t *s_red);
+// Bits needed for values up to r (0 for r == 0).
+__device__ __forceinline__ int value_bits(uint32_t r) { return r ? 32 - __clz((int)r) : 0; }
 
 // Write the sorted data of split window w to HBM (layout at kSortedWords),
-// make it visible to every CU, then raise the window's ready flag.
-__device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_t *s_red)
+// make it visible to every CU, then raise the window's ready flag.  Two
+// sorts, each one radix sort in LDS: x (keys ((X - min_x) << nb) | i, or with
+// 64-bit keys the offsets X - min_x) and y (offsets Y - min_y).
+__device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_t *s_red, uint32_t *s_cnt)
 {
     const WinDesc d = a.win[w];
     const int m = (int)d.m;
     const int tid = threadIdx.x;
     int32_t *out = a.sorted + (uint64_t)kSortedWords * d.sorted_off;
-    int32_t *scratch = reinterpret_cast<int32_t *>(buf);
     const WinAux ax = window_aux(d, s_red);
-    if (ax.nb) {
-        // keys ((X - min_x) << nb) | i; the sign bit is flipped for the signed
-        // sort so that signed order is unsigned key order
-        int P = 1;
-        while (P < m)
-            P <<= 1;
+    const uint32_t mask = (1u << ax.nb) - 1u;
+    for (int job = 0; job < 2; ++job) {
+        const float *v = job ? d.y : d.x;
+        const int32_t mn = job ? ax.min_y : ax.min_x;
+        // keys carrying the index are built in index order: sorting the bits
+        // from nb up stably gives the order of the whole key
+        const uint32_t shift = job ? 0u : ax.nb;
         uint32_t off = 0;
         block_sync();
-        for (int i = tid; i < P; i += kBlock)
-            scratch[i] = i < m ? (int32_t)((((uint32_t)(grid_int(d.x[i], off) - ax.min_x) << ax.nb) | (uint32_t)i) ^
-                                           0x80000000u)
-                               : INT32_MAX;
-        bitonic_lds<kMaxWindow / (2 * kBlock), 1>(scratch, nullptr, (uint32_t)P, (uint32_t)P);
-        const uint32_t mask = (1u << ax.nb) - 1u;
-        for (int s = tid; s < m; s += kBlock) {
-            const uint32_t key = (uint32_t)scratch[s] ^ 0x80000000u;
-            const uint32_t j = key & mask;
-            out[s] = (int32_t)key;
-            out[m + s] = (int32_t)((uint32_t)(grid_int(d.y[j], off) - ax.min_y) << ax.nb);
+        for (int i = tid; i < m; i += kBlock)
+            buf[i] = ((uint32_t)(grid_int(v[i], off) - mn) << shift) | (shift ? (uint32_t)i : 0u);
+        radix_lds(buf, m, (int)shift, (value_bits(job ? ax.range_y : ax.range_x) + 3) / 4, s_cnt);
+        if (shift) {
+            for (int s = tid; s < m; s += kBlock) {
+                const uint32_t key = buf[s];
+                out[s] = (int32_t)key;
+                out[m + s] = (int32_t)((uint32_t)(grid_int(d.y[key & mask], off) - ax.min_y) << ax.nb);
+            }
+        } else {
+            int32_t *dst = job ? out + 2 * m : out;
+            for (int s = tid; s < m; s += kBlock)
+                dst[s] = (int32_t)buf[s] + mn;
         }
-    } else {
-        sort_marginal(d.x, m, scratch, out);
     }
-    sort_marginal(d.y, m, scratch, out + 2 * m);
     __threadfence();
     block_sync();
     if (threadIdx.x == 0)
@@ -521,6 +581,8 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
     const uint32_t nb = ceil_log2((uint32_t)(m > 1 ? m : 2));
     // 32-bit keys need (range << nb) + j < 2^32
     ax.nb = (((rx | ry) >> (32 - nb)) == 0u) ? nb : 0u;
+    ax.range_x = rx;
+    ax.range_y = ry;
     ax.flags = s_red[4] ? kFlagOffGrid : 0u;
     block_sync();
     return ax;
@@ -1433,6 +1495,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
     __shared__ LocalShared L;
     __shared__ long long s_part[kBlock / 64];
     __shared__ int32_t s_red[5];
+    __shared__ uint32_t s_cnt[64];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
 
@@ -1459,7 +1522,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
             // a sort that split items of the window will wait for: its waves
             // issue ahead of theirs
             __builtin_amdgcn_s_setprio(3);
-            prep_item(a, itm.win, buf, s_red);
+            prep_item(a, itm.win, buf, s_red, s_cnt);
             __builtin_amdgcn_s_setprio(0);
         } else {
             // split items are the largest, taken first: let their waves issue
@@ -1526,9 +1589,10 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint32_t buf[kMaxWindow];
     __shared__ int32_t s_red[5];
+    __shared__ uint32_t s_cnt[64];
     const uint32_t pi = a.win_begin + blockIdx.x;
     if (pi < a.n_prep)
-        prep_item(a, a.prep_list[pi], buf, s_red);
+        prep_item(a, a.prep_list[pi], buf, s_red, s_cnt);
 }
 
 // --------------------------------------------------------------------------
