@@ -43,6 +43,11 @@ constexpr uint32_t kItemLocal = 0x80000000u;
 constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
 constexpr uint32_t kErrWait = 1u;            // error word: a dependency wait gave up
+// ready word of a split window, written by its prep item once the sorted data
+// is in HBM: kReady, kReadyOffGrid if a value is off the grid, and the key
+// index bits nb (0: 64-bit keys) from kReadyNbShift
+constexpr uint32_t kReady = 1u, kReadyOffGrid = 2u;
+constexpr uint32_t kReadyNbShift = 8;
 // Sorted data of a split window (kSortedWords x m words from sorted_off):
 //   [0, m)   32-bit keys: ((X - min_x) << nb) | i in ascending order (the
 //            points in x order, each with its index); with nb == 0 (64-bit
@@ -71,7 +76,7 @@ struct QDesc {              // 16 bytes
     double tau_eff;         // noise threshold, already normalised if requested
 };
 
-struct WinAux {             // per split item, computed by the item itself
+struct WinAux {             // per split window: from its values (prep), or its ready word and sorted data
     int32_t min_x, min_y;   // window minima of the grid integers
     uint32_t nb;            // index bits in a 32-bit key; 0 selects 64-bit keys
     uint32_t flags;         // kFlagOffGrid

@@ -395,7 +395,7 @@ __device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_
     __threadfence();
     block_sync();
     if (threadIdx.x == 0)
-        atomicExch(&a.ready[w], 1u);
+        atomicExch(&a.ready[w], kReady | (ax.flags ? kReadyOffGrid : 0u) | (ax.nb << kReadyNbShift));
 }
 
 // --------------------------------------------------------------------------
@@ -588,24 +588,44 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
     return ax;
 }
 
-// Wait until window w's sorted data is in HBM.  The prep item has a lower
-// index than every split item, so a running workgroup already holds it and it
-// waits on nothing: the wait ends.  A poll limit turns a broken dependency
-// into an error report instead of a hang.
-__device__ void wait_ready(const LaunchArgs &a, uint32_t w)
+// Wait until window w's sorted data is in HBM and return the window's
+// constants: nb and the off-grid flag from its ready word, min_y as the first
+// sorted y integer, min_x from the point that starts the x order (or the
+// first sorted x integer with 64-bit keys).  The prep item has a lower index
+// than every split item, so a running workgroup already holds it and it waits
+// on nothing: the wait ends.  A poll limit turns a broken dependency into an
+// error report instead of a hang.
+__device__ WinAux split_window_aux(const LaunchArgs &a, uint32_t w, const WinDesc &d, int32_t *s_red)
 {
     if (threadIdx.x == 0) {
-        uint32_t polls = 0;
-        while (atomicAdd(&a.ready[w], 0u) == 0u) {
+        uint32_t polls = 0, v;
+        while ((v = atomicAdd(&a.ready[w], 0u)) == 0u) {
             if (++polls >= kWaitLimit) {
                 atomicOr(a.err, kErrWait);
                 break;
             }
             __builtin_amdgcn_s_sleep(8);
         }
+        s_red[0] = (int32_t)v;
     }
     block_sync();
     __threadfence();  // acquire: later loads see the prep item's stores
+    const uint32_t v = (uint32_t)s_red[0];
+    const int m = (int)d.m;
+    const int32_t *base = a.sorted + (uint64_t)kSortedWords * d.sorted_off;
+    WinAux ax;
+    ax.nb = (v >> kReadyNbShift) & 31u;
+    ax.flags = (v & kReadyOffGrid) ? kFlagOffGrid : 0u;
+    ax.min_y = base[2 * m];
+    if (ax.nb) {
+        uint32_t off = 0;
+        ax.min_x = grid_int(d.x[(uint32_t)base[0] & ((1u << ax.nb) - 1u)], off);
+    } else {
+        ax.min_x = base[0];
+    }
+    ax.range_x = ax.range_y = 0u;  // not needed by split items
+    block_sync();  // s_red is reused
+    return ax;
 }
 
 constexpr int kChunk = 2048;  // candidates (and sorted-marginal entries) staged in LDS at a time
@@ -722,7 +742,6 @@ __device__ __forceinline__ long long split_body_wide(const LaunchArgs &a, uint32
         split_radii<K, unsigned long long>(top[q], (unsigned long long)min(q0 + tid + q * kBlock, m - 1), 12,
                                            0xFFFu, d, ax, qx[q], qy[q], a.estimator, rx[q], ry[q]);
     // ---- marginal counts over the sorted marginals, chunk by chunk
-    wait_ready(a, w);
     int32_t xi[Q], yi[Q];
     int hx[Q], lx[Q], hy[Q], ly[Q];
 #pragma unroll
@@ -928,7 +947,6 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
     const int m = (int)d.m;
     const int tid = threadIdx.x;
     const uint32_t nb = ax.nb, mask = (1u << nb) - 1u;
-    wait_ready(a, w);
     const uint32_t *KX = reinterpret_cast<const uint32_t *>(a.sorted + (uint64_t)kSortedWords * d.sorted_off);
     const uint32_t *YS = KX + m;
     const int32_t *SY = reinterpret_cast<const int32_t *>(KX + 2 * m);
@@ -1105,7 +1123,7 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *bu
                            int32_t *s_red)
 {
     const WinDesc d = a.win[w];
-    const WinAux ax = window_aux(d, s_red);
+    const WinAux ax = split_window_aux(a, w, d, s_red);
     const int m = (int)d.m;
     const int tid = threadIdx.x;
     long long part = 0;
