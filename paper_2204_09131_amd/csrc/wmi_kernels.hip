@@ -896,7 +896,7 @@ __device__ __forceinline__ uint64_t key_below(int64_t v, uint32_t nb)
 
 // A wave stops its shared scan once at most this many of its query slots can
 // still gain from a side; those finish one at a time with the whole wave.
-constexpr int kStragglers = 4;
+constexpr int kStragglers = 16;
 
 // One straggler's scan of one side, by the whole wave: candidates from `edge`
 // outwards (RIGHT: edge, edge + 1, ...; left: edge - 1, edge - 2, ...), 256
