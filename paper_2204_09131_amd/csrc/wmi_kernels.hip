@@ -824,8 +824,25 @@ template <int K, bool SELF>
 __device__ __forceinline__ void scan_wave(const uint4 *__restrict__ wb, int cnt, const uint32_t (&qx)[2],
                                           const uint32_t (&qy)[2], const uint32_t (&qj)[2], uint32_t (&top)[2][K])
 {
-#pragma unroll 2
-    for (int i = 0; i < cnt; ++i) {
+    // four candidates a step: their LDS reads are in flight together
+    int i = 0;
+    for (; i + 4 <= cnt; i += 4) {
+        uint4 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            c[u] = wb[i + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                uint32_t k = tmax(sad_key_v(qx[t], c[u].x, c[u].z), sad_key_v(qy[t], c[u].y, c[u].z));
+                if (SELF)
+                    k = c[u].z == qj[t] ? 0xFFFFFFFFu : k;
+                insert_sorted<K>(top[t], k);
+            }
+        }
+    }
+    for (; i < cnt; ++i) {
         const uint4 c = wb[i];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
