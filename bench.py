@@ -46,8 +46,8 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # same counter reads for an elementwise kernel of known traffic (256 MiB read,
 # 256 MiB written): FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0.  Valid only for the
 # kernel source it was taken on (hash of the kernel and descriptor sources).
-TRAFFIC = {"kernel_sha256": "686e33a92f82019f477f1b703b87566c2dcb3ea412fbaa11176c894f55988bb4",
-           "fetch_bytes": 68068589, "write_bytes": 31237734}
+TRAFFIC = {"kernel_sha256": "879728f4d31d3e3c193c22e361310a334780f481b61da6ce6b902f90a42afa1e",
+           "fetch_bytes": 78583189, "write_bytes": 46743756}
 
 
 def kernel_source_hash() -> str:
@@ -299,7 +299,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
