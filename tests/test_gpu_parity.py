@@ -78,6 +78,9 @@ COUNT_CASES = [
     (511, 3, 0, "grid", 8), (512, 4, 0, "normal", 9), (513, 4, 0, "grid", 10), (1000, 5, 1, "normal", 11),
     (1024, 4, 0, "grid", 12), (2049, 4, 0, "normal", 13), (4096, 4, 0, "normal", 14),
     (4096, 16, 1, "grid", 15), (3000, 4, 0, "wide", 16), (700, 8, 1, "wide", 17),
+    # heavy-tailed y: many queries whose k-th neighbour is far, so the x-order
+    # scans of windows above 512 points end with many stragglers on both sides
+    (4096, 4, 0, "heavy", 18), (2048, 7, 1, "heavy", 19), (1500, 16, 0, "heavy", 20),
 ]
 
 
@@ -86,6 +89,11 @@ def make_window(m, kind, seed):
         return synth.grid_points(m, seed, levels=6, scale=1 / 64)
     if kind == "normal":
         return synth.bivariate_normal(m, 0.6, seed)
+    if kind == "heavy":
+        r = synth.rng(seed)
+        x = r.standard_normal(m)
+        y = r.standard_normal(m) / (r.uniform(0.0, 1.0, m) + 0.02)
+        return synth.quantize(x), synth.quantize(y / 8.0)
     if kind == "wide":  # value range too large for 32-bit keys at this m
         x, y = synth.bivariate_normal(m, 0.6, seed, scale=300.0)
         return x, y
