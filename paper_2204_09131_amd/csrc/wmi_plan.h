@@ -137,10 +137,16 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
 
 // Batched form: the queue the persistent kernel takes items from.  Prep
 // items (one per split window, largest first) come first, then the local
-// items, then the split items, each class largest cost first (a stable bucket
-// order by log2(cost) is enough for the greedy schedule).  A split item scans
-// its window in x order, which its prep item writes: the local items in
-// between keep the device busy while those sorts finish.
+// items, then the split items, then the local items cheaper than kTailCost,
+// each class largest cost first (a stable bucket order by log2(cost) is
+// enough for the greedy schedule).  A split item scans its window in x order,
+// which its prep item writes: the local items in between keep the device busy
+// while those sorts finish, and the cheap ones at the end shorten the tail
+// that the last, long split items would leave.  kTailCost (in the cost units
+// of plan_items: m^2 + 4096 per window) puts the items of windows up to 128
+// points there.
+constexpr uint64_t kTailCost = 100000;
+
 inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vector<Item> &queue)
 {
     queue.clear();
@@ -150,14 +156,19 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
     for (uint32_t w : prep)
         queue.push_back(Item{w, kItemPrep});
     auto bucket = [](uint64_t c) { return 63 - (63 - __builtin_clzll(c | 1ull)); };
-    for (int local = 1; local >= 0; --local) {
+    // phase 0: local items; 1: split items; 2: the cheapest local items,
+    // which end the queue and fill the device while the last split items run
+    for (int phase = 0; phase < 3; ++phase) {
         std::vector<uint32_t> cnt(66, 0);
         std::vector<size_t> idx;
-        for (size_t i = 0; i < P.items.size(); ++i)
-            if (((P.items[i].info & kItemLocal) != 0) == (local == 1)) {
+        for (size_t i = 0; i < P.items.size(); ++i) {
+            const bool local = (P.items[i].info & kItemLocal) != 0;
+            const int ph = local ? (P.cost[i] < kTailCost ? 2 : 0) : 1;
+            if (ph == phase) {
                 cnt[bucket(P.cost[i]) + 1]++;
                 idx.push_back(i);
             }
+        }
         for (int i = 1; i <= 65; ++i)
             cnt[i] += cnt[i - 1];
         const size_t base = queue.size();
