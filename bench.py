@@ -46,7 +46,7 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # same counter reads for an elementwise kernel of known traffic (256 MiB read,
 # 256 MiB written): FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0.  Valid only for the
 # kernel source it was taken on (hash of the kernel and descriptor sources).
-TRAFFIC = {"kernel_sha256": "879728f4d31d3e3c193c22e361310a334780f481b61da6ce6b902f90a42afa1e",
+TRAFFIC = {"kernel_sha256": "72f4d7cb4ea5e1639cceedfe97c7b030240757839d1d1375b25d23a089fb73dd",
            "fetch_bytes": 78583189, "write_bytes": 46743756}
 
 

@@ -10,7 +10,8 @@
 //
 // No MFMA anywhere: a max-norm neighbour search is not a contraction; the
 // bound is the 32-bit VALU.  A persistent kernel takes items from an atomic
-// counter; the queue holds prep items, then local items, then split items:
+// counter; the queue holds prep items, then local items, then split items,
+// then the cheapest local items (the host's plan decides the order):
 //
 //   local item  up to 16 consecutive windows of at most 512 points in total
 //               (whole queries, noise triples included, where they fit).
