@@ -43,6 +43,14 @@ MUTANTS = {
     "k_minus_one_neighbours": ("for (int r = 0; r < k; ++r) {\n            int best_j", "for (int r = 0; r < k - 1; ++r) {\n            int best_j"),
     "noise_ext_compare": ("r.mi_ext < tau_eff && r.mi_union < r.mi_base", "r.mi_ext < tau_eff && r.mi_union > r.mi_base"),
     "noise_ext_side_swapped": ("q->start + q->len : q->start - q->ext_len", "q->start - q->ext_len : q->start + q->len"),
+    # the normalised threshold tau * ln|w_d| of the new part
+    "tau_norm_log2": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
+                      "tau_normalize ? tau * log2((double)q->ext_len) : tau"),
+    "tau_norm_union": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
+                       "tau_normalize ? tau * log((double)(q->len + q->ext_len)) : tau"),
+    "tau_norm_base": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
+                      "tau_normalize ? tau * log((double)q->len) : tau"),
+    "tau_norm_ignored": ("tau_normalize ? tau * log((double)q->ext_len) : tau", "tau"),
 }
 
 
@@ -96,6 +104,14 @@ def pin_suite(orc):
     res = orc.batch([xq, yq], q, k=4, tau=0.1)[0]
     assert res["mi_ext"] == orc.window_mi(xq[256:512], yq[256:512], 4, 0)
     assert res["flags"] & oracle.FLAG_NOISE
+    # normalised threshold tau * ln|w_d| on the X-shaped triple (closed forms
+    # I(w_d) = psi(8) - psi(4) - 1/4 = 0.5095 against tau ln 8)
+    from test_oracle_pins import _x_shape_triple
+    x, y = _x_shape_triple()
+    q = synth.make_queries(0, 1, 0, 16, 8, +1)
+    for tau, noise in ((0.22, False), (0.30, True)):
+        res = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=1)[0]
+        assert bool(res["flags"] & oracle.FLAG_NOISE) == noise
 
 
 @pytest.fixture(scope="module")

@@ -360,3 +360,57 @@ def test_offgrid_flag():
     y[5] += np.float32(1e-5)
     res = orc.batch([x, y], synth.make_queries(0, 1, 0, 64), k=4)
     assert res[0]["flags"] & oracle.FLAG_OFFGRID
+
+
+# ---------------------------------------------------------------------------
+# the normalised noise threshold: tau * ln|w_d| (Eq. normalizedMI with the
+# entropy of |w_d| distinct samples, applied to Definition 6.2's new part)
+# ---------------------------------------------------------------------------
+
+def _x_shape_triple():
+    """A 16-point ramp (y = x) followed by an 8-point anti-diagonal over the
+    same x range.  Each part alone is a tie-free scaled ramp, so by the closed
+    form I(w_o) = psi(16) - psi(4) - 1/4 = 1.23490 and
+    I(w_d) = psi(8) - psi(4) - 1/4 = 0.50952; the union is an X, whose
+    estimate (0.27023 by the full-sort brute force) is far below I(w_o)."""
+    u = 1.0 / 4096.0
+    j = np.arange(8)
+    x = np.concatenate([np.arange(16) * u, 2 * j * u]).astype(np.float32)
+    y = np.concatenate([np.arange(16) * u, (15 - 2 * j) * u]).astype(np.float32)
+    return x, y
+
+
+def test_x_shape_triple_parts_by_closed_form_and_brute_force():
+    x, y = _x_shape_triple()
+    assert brute_mi(x[:16], y[:16], 4, 0) == pytest.approx(digamma(16) - digamma(4) - 0.25, abs=1e-12)
+    assert brute_mi(x[16:], y[16:], 4, 0) == pytest.approx(digamma(8) - digamma(4) - 0.25, abs=1e-12)
+    assert brute_mi(x, y, 4, 0) == pytest.approx(0.2702282595235883, abs=1e-12)
+
+
+# tau, expected noise bit with tau * ln|w_d|; the readings a slip could take
+# instead (ln|w_o|, ln|w''|, log2|w_d|, log10|w_d|, no normalisation) give
+# the opposite bit in at least one of the two cases, which the test asserts.
+@pytest.mark.parametrize("tau,noise", [(0.22, False), (0.30, True)])
+def test_noise_flag_normalized_threshold(orc, tau, noise):
+    import oracle
+    x, y = _x_shape_triple()
+    i_o = digamma(16) - digamma(4) - 0.25
+    i_d = digamma(8) - digamma(4) - 0.25
+    # the case sits well clear of its threshold under the paper's reading
+    assert abs(i_d - tau * math.log(8)) > 0.04
+    assert (i_d < tau * math.log(8)) == noise
+    # and the wrong readings are told apart by the pair of cases
+    wrong = {"ln|w_o|": tau * math.log(16), "ln|w''|": tau * math.log(24), "log2": tau * 3.0,
+             "log10": tau * math.log10(8), "raw": tau}
+    flips = {name for name, thr in wrong.items() if (i_d < thr) != noise}
+    assert flips == ({"ln|w_o|", "ln|w''|", "log2"} if not noise else {"log10", "raw"})
+    q = synth.make_queries(0, 1, 0, 16, 8, +1)
+    r = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=1)[0]
+    assert r["mi_base"] == pytest.approx(i_o, abs=1e-12)
+    assert r["mi_ext"] == pytest.approx(i_d, abs=1e-12)
+    assert r["mi_union"] == pytest.approx(0.2702282595235883, abs=1e-12)
+    assert bool(r["flags"] & oracle.FLAG_NOISE) == noise
+    assert not r["flags"] & oracle.FLAG_NONPOS_BASE
+    # without normalisation the raw threshold decides: never noise here
+    r = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=0)[0]
+    assert not r["flags"] & oracle.FLAG_NOISE

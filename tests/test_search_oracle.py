@@ -137,3 +137,93 @@ def test_bottom_up_left_pruning_by_hand():
     trace0 = []
     search.bottom_up(mi, 0, 96, 32, 64, 16, 0.05, max_idle=0, history=1, tau=0.1, p=0, trace=trace0)
     assert trace0[8:11] == [(16, 48), (16, 64), (16, 80)]  # without pruning the left side stays open
+
+
+# ---------------------------------------------------------------------------
+# normalised thresholds: sigma ln|w| for a correlated window, tau ln|w_d| for
+# the new part of a shifted or extended window (Eq. normalizedMI with the
+# entropy of |w| distinct samples)
+# ---------------------------------------------------------------------------
+
+def td_normalized_noise_case(srch, v):
+    """Top-down, one layer of 64-point windows, step 8, p = 1, tau = 0.1,
+    nothing correlated (sigma ln 64 = 41.6).  The new part scores v against
+    tau ln 8 = 0.2079: v = 0.15 is noise (and would not be under the raw
+    threshold 0.1 or 0.1 log10 8 = 0.090), v = 0.25 is not (and would be
+    under 0.1 log2 8 = 0.3, 0.1 ln 64 = 0.416 or 0.1 ln 56 = 0.403)."""
+    vals = {64: 0.3, 56: 0.4, 8: v}
+    trace = []
+    srch.top_down(lambda t, m: vals[m], 0, 200, 64, 64, 10.0, tau=0.1, p=1, normalize=True, trace=trace)
+    return [t for _, t in trace]
+
+
+def bu_normalized_noise_case(srch, v):
+    """The left-pruning climb below with normalised thresholds: windows of 32
+    points or more score start / 1000, the 16-point new parts score v against
+    tau ln 16 = 0.2773 (tau = 0.1).  v = 0.2 is noise, so the left side closes
+    in the ring of [16, 48); v = 0.3 is not, so it stays open.  The raw
+    threshold (0.1) would keep it open at 0.2; 0.1 log2 16 = 0.4, 0.1 ln 48
+    (the union) = 0.387 and 0.1 ln 32 (the base) = 0.347 would close it at
+    0.3.  sigma ln 32 = 0.0347 reports the final [64, 96) (I = 0.064)."""
+    def mi(s, m):
+        return s / 1000.0 if m >= 32 else v
+    trace = []
+    found = srch.bottom_up(mi, 0, 96, 32, 64, 16, 0.01, max_idle=0, history=1, tau=0.1, p=1, normalize=True,
+                           trace=trace)
+    return found, trace
+
+
+def bu_normalized_report_case(srch, sigma):
+    """Hill climb of I = |w| / 1000 ending at 128-point windows (I = 0.128):
+    reported iff 0.128 >= sigma ln 128, i.e. for sigma = 0.026 (0.1262) and
+    not for sigma = 0.027 (0.1310); sigma log2 128 = 0.182 would report
+    neither, the raw sigma both."""
+    found = srch.bottom_up(lambda s, m: m / 1000.0, 0, 300, 64, 128, 16, sigma, max_idle=1, history=1,
+                           normalize=True)
+    return [(s, m) for s, m, _, _ in found]
+
+
+PRUNED_LEFT_TRACE = [(0, 32), (0, 48), (16, 48), (0, 32), (0, 48), (0, 64), (16, 64), (32, 64), (32, 80),
+                     (48, 80), (48, 96), (64, 96)]
+
+
+def normalized_pin_suite(srch):
+    assert td_normalized_noise_case(srch, 0.15) == [0, 8, 72, 80]
+    assert td_normalized_noise_case(srch, 0.25) == list(range(0, 137, 8))
+    found, trace = bu_normalized_noise_case(srch, 0.2)
+    assert trace == PRUNED_LEFT_TRACE and [(s, m) for s, m, _, _ in found] == [(64, 32)]
+    found, trace = bu_normalized_noise_case(srch, 0.3)
+    assert trace[8:11] == [(16, 48), (16, 64), (16, 80)]
+    assert bu_normalized_report_case(srch, 0.026) == [(0, 128), (128, 128)]
+    assert bu_normalized_report_case(srch, 0.027) == []
+
+
+def test_normalized_noise_and_report_thresholds():
+    normalized_pin_suite(search)
+
+
+SEARCH_MUTANTS = {
+    "td_noise_log2": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log2(delta)"),
+    "td_noise_window": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log(s_w)"),
+    "td_noise_overlap": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log(s_w - delta)"),
+    "td_noise_raw": ("noise_thr = tau * math.log(delta) if normalize else tau", "noise_thr = tau"),
+    "bu_noise_log2": ("thr = tau * math.log(ext) if normalize else tau",
+                      "thr = tau * math.log2(ext) if normalize else tau"),
+    "bu_noise_union": ("thr = tau * math.log(ext) if normalize else tau",
+                       "thr = tau * math.log(e - s) if normalize else tau"),
+    "bu_noise_raw": ("thr = tau * math.log(ext) if normalize else tau", "thr = tau"),
+    "bu_report_log2": ("thr_w = sigma * math.log(we - ws)", "thr_w = sigma * math.log2(we - ws)"),
+    "bu_report_raw": ("thr_w = sigma * math.log(we - ws) if normalize else sigma", "thr_w = sigma"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SEARCH_MUTANTS))
+def test_search_mutant_is_caught(name):
+    import types
+    old, new = SEARCH_MUTANTS[name]
+    text = open(search.__file__).read()
+    assert text.count(old) >= 1, name
+    mod = types.ModuleType("search_mutant_" + name)
+    exec(compile(text.replace(old, new), search.__file__ + ":" + name, "exec"), mod.__dict__)
+    with pytest.raises(AssertionError):
+        normalized_pin_suite(mod)
