@@ -34,9 +34,22 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+# The main kernel is instantiated once per k (1..16) in a unit of its own:
+# wmi_kernels.hip compiled again with WMI_MAIN_K = k.
+MAIN_KS = range(1, 17)
+
+
+def _units():
+    units = [(src, ()) for src in SOURCES]
+    units += [("wmi_kernels.hip", (f"-DWMI_MAIN_K={k}",)) for k in MAIN_KS]
+    return units
+
+
+def _compile(unit) -> str:
+    src, defs = unit
+    tag = "_".join(d.split("=")[-1] for d in defs)
+    obj = os.path.join(BUILD_DIR, os.path.basename(src) + (f".k{tag}" if tag else "") + ".o")
+    cmd = [_hipcc(), *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -46,8 +59,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, _units()))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

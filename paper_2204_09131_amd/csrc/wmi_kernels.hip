@@ -96,6 +96,19 @@ __device__ __forceinline__ void count_evals(const LaunchArgs &a, int n_live, int
         atomicAdd(&a.evals[blockIdx.x], (unsigned long long)n_live * (unsigned long long)per_query);
 }
 
+// Same with a per-lane count: the wave's lanes add `mine` each (only when
+// counting).  Every lane of the wave calls it.
+__device__ __forceinline__ void count_evals_lanes(const LaunchArgs &a, uint32_t mine)
+{
+    if (!a.evals)
+        return;
+    unsigned long long v = mine;
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v > 0)
+        atomicAdd(&a.evals[blockIdx.x], v);
+}
+
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T>
@@ -111,6 +124,33 @@ __device__ __forceinline__ void insert_sorted(T (&t)[S], T key)
     for (int r = S - 1; r >= 1; --r)
         t[r] = med3(t[r - 1], t[r], key);
     t[0] = tmin(t[0], key);
+}
+
+// The same for 32-bit keys, one v_med3_u32 / v_min_u32 per entry.  Written
+// as asm (plain arithmetic, no memory access) so that loop analysis does not
+// expand the lists as nested min/max expressions: across an unrolled scan
+// those grow with every insertion and made compile time explode for k >= 14.
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_min_u32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+template <int S>
+__device__ __forceinline__ void insert_sorted(uint32_t (&t)[S], uint32_t key)
+{
+#pragma unroll
+    for (int r = S - 1; r >= 1; --r)
+        t[r] = med3_u32(t[r - 1], t[r], key);
+    t[0] = min_u32(t[0], key);
 }
 
 // Grid integer of a value; flags values off the 2^-12 grid or out of range.
@@ -195,6 +235,7 @@ __device__ __forceinline__ long long point_terms(const LaunchArgs &a, int hx, in
     return a.psi_fix[cx + 1] + a.psi_fix[cy + 1];
 }
 
+#ifndef WMI_MAIN_K
 // --------------------------------------------------------------------------
 // clear: zero the counters and accumulators of a launch
 // --------------------------------------------------------------------------
@@ -214,6 +255,7 @@ __global__ void clear_kernel(LaunchArgs a)
     if (t == 0)
         a.counter[0] = 0u;
 }
+#endif  // !WMI_MAIN_K
 
 // --------------------------------------------------------------------------
 // prep: sorted marginals of a split window (one workgroup)
@@ -1453,8 +1495,9 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             const int mode = __builtin_amdgcn_readfirstlane(
                 nb_min == 0u ? 3 : (w_min == w_max ? 0 : (m_max == m_min ? 1 : 2)));
             local_knn2<K>(cand, L.off[wl], m, il, nb, mode, m_max, band0, a.estimator, RX, RY);
-            const int n_live = __popcll(__ballot(live)) + __popcll(__ballot(live && act[1]));
-            count_evals(a, n_live, m_max - 1);
+            // each live slot needs the m - 1 other points of its own window;
+            // candidates a wave scans past a lane's window are padding
+            count_evals_lanes(a, live ? (uint32_t)(m - 1) * (act[1] ? 2u : 1u) : 0u);
         }
     }
     block_sync();
@@ -1577,6 +1620,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
     }
 }
 
+#ifndef WMI_MAIN_K
 // --------------------------------------------------------------------------
 // serving: expand range parts into windows, queries and queue items
 // --------------------------------------------------------------------------
@@ -1705,23 +1749,35 @@ hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int K>
-static hipError_t launch_main_k(const LaunchArgs &a, uint32_t grid, hipStream_t s)
+#endif  // !WMI_MAIN_K
+
+// The main kernel is instantiated once per k, each in its own translation
+// unit (this file compiled with WMI_MAIN_K = k), so the sixteen variants
+// compile in parallel; the unit without WMI_MAIN_K dispatches on k.
+#define WMI_PASTE2(a, b) a##b
+#define WMI_PASTE(a, b) WMI_PASTE2(a, b)
+#define WMI_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+#ifdef WMI_MAIN_K
+hipError_t WMI_PASTE(launch_main_k, WMI_MAIN_K)(const LaunchArgs &a, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(main_kernel<K>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(main_kernel<WMI_MAIN_K>, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
-template <int K>
-static int occupancy_k()
+int WMI_PASTE(main_occupancy_k, WMI_MAIN_K)()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, main_kernel<K>, kBlock, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, main_kernel<WMI_MAIN_K>, kBlock, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
-
-#define WMI_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#else
+#define X(KK)                                                                      \
+    hipError_t launch_main_k##KK(const LaunchArgs &a, uint32_t grid, hipStream_t s); \
+    int main_occupancy_k##KK();
+WMI_K_CASES(X)
+#undef X
 
 hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s)
 {
@@ -1730,7 +1786,7 @@ hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s)
     switch (a.k) {
 #define X(KK)  \
     case KK:   \
-        return launch_main_k<KK>(a, grid, s);
+        return launch_main_k##KK(a, grid, s);
         WMI_K_CASES(X)
 #undef X
     default:
@@ -1743,12 +1799,13 @@ int main_occupancy(uint32_t k)
     switch (k) {
 #define X(KK) \
     case KK:  \
-        return occupancy_k<KK>();
+        return main_occupancy_k##KK();
         WMI_K_CASES(X)
 #undef X
     default:
         return 1;
     }
 }
+#endif
 
 }  // namespace wmi
