@@ -223,10 +223,12 @@ int wmi_batch_stats_get(wmi_batch *batch, wmi_batch_stats *out);
  * once more (results are rewritten with the same values) with a per-workgroup
  * counter and writes to *evaluated the number of (query point, candidate)
  * distances the neighbour searches computed for live query points, the point
- * itself excluded.  The estimator's definition (Eq. 2) asks for the k nearest
- * of all m - 1 other points, so m (m - 1) per window is the brute-force count;
- * split windows scan outwards in x order and stop early, so the count is
- * lower there.  Synchronous on the batch's stream; allocates 8 bytes per
+ * itself excluded, each query point counting candidates of its own window
+ * only (a wave holding several short windows also scans padding past a
+ * lane's window; those keys are masked and not counted).  The estimator's
+ * definition (Eq. 2) asks for the k nearest of all m - 1 other points, so
+ * m (m - 1) per window is the brute-force count; windows above 512 points
+ * scan outwards in x order and stop early, so the count is lower there.  Synchronous on the batch's stream; allocates 8 bytes per
  * main-kernel workgroup for the call.  WMI_EINVAL for plain batches.
  */
 int wmi_batch_count_evals(wmi_batch *batch, uint64_t *evaluated);
@@ -300,10 +302,13 @@ typedef struct {
     uint64_t windows_done;
     uint64_t ordered_pairs_done;
     uint64_t launches;
-    double busy_us;              /* sum of launch durations (events)            */
+    double busy_us;              /* sum of launch durations (events); launches of
+                                    the two slots overlap, so it can exceed wall time */
     uint64_t arena_bytes;        /* admission budget                             */
     uint64_t arena_peak_bytes;   /* most arena bytes held at once                */
     uint64_t queued_peak;        /* most requests waiting for admission at once   */
+    double busy_union_us;        /* device time with at least one launch running
+                                    (union of the launch intervals; <= wall time) */
 } wmi_server_stats;
 
 /* Start a server on a store (its series stay owned by the store; a series

@@ -98,6 +98,7 @@ struct Req {
     uint64_t nwin = 0, next = 0, done = 0, pairs = 0;
     uint64_t arena_off = 0;
     bool has_arena = false;
+    bool pinned = false;  // holds a reader count on series a and b (store mutex)
     int32_t state = 0;  // 0 queued, 1 admitted, 3 copying, 2 done, < 0 error
     double t_arrival = 0, t_admit = 0, t_first = 0, t_complete = 0;
     uint32_t launches = 0, inflight = 0;
@@ -134,6 +135,8 @@ struct wmi_server {
     ArenaAlloc arena;
     Slot slots[2];
     hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_origin = nullptr;  // device-time origin of the launch intervals
+    std::vector<std::pair<float, float>> intervals;  // launch [start, end) in ms after ev_origin
     int occupancy = 1;
     std::thread th;
     std::mutex mu;
@@ -187,9 +190,14 @@ void fail_all(wmi_server *S, int code)
     S->cv.notify_all();
 }
 
-void unpin(wmi_server *S, const Req *r)
+// Give back the request's reader counts on its series, once: a request that
+// failed after its download may reach here again from destroy.
+void unpin(wmi_server *S, Req *r)
 {
     std::lock_guard<std::mutex> lk(S->st->mu);
+    if (!r->pinned)
+        return;
+    r->pinned = false;
     for (uint32_t id : {r->r.a, r->r.b})
         if (id < S->st->series.size() && S->st->series[id].busy)
             S->st->series[id].busy--;
@@ -354,12 +362,16 @@ void scheduler(wmi_server *S)
                 fail_all(S, WMI_EHIP);
                 break;
             }
-            float ms = 0.f;
+            float ms = 0.f, t_start = 0.f, t_end = 0.f;
             (void)hipEventElapsedTime(&ms, slot.ev0, slot.ev1);
+            const bool have_iv = hipEventElapsedTime(&t_start, S->ev_origin, slot.ev0) == hipSuccess &&
+                                 hipEventElapsedTime(&t_end, S->ev_origin, slot.ev1) == hipSuccess;
             uint32_t err = 0;
             std::memcpy(&err, slot.host + slot.h_err, sizeof err);
             std::lock_guard<std::mutex> lk(S->mu);
             S->stats.busy_us += 1e3 * ms;
+            if (have_iv)
+                S->intervals.emplace_back(t_start, t_end);
             S->stats.launches++;
             for (const Part &p : slot.parts) {
                 Req *r = p.r;
@@ -478,6 +490,12 @@ int wmi_server_create(wmi_store *st, const wmi_server_desc *desc, wmi_server **o
         if (e == hipSuccess)
             e = hipEventCreate(&slot.ev1);
     }
+    if (e == hipSuccess)
+        e = hipEventCreate(&S->ev_origin);
+    if (e == hipSuccess)
+        e = hipEventRecord(S->ev_origin, S->slots[0].stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(S->ev_origin);
     if (e != hipSuccess) {
         int rc = fail(WMI_EHIP, "wmi_server_create: %s", hipGetErrorString(e));
         for (Slot &slot : S->slots) {
@@ -490,6 +508,7 @@ int wmi_server_create(wmi_store *st, const wmi_server_desc *desc, wmi_server **o
         if (S->arena_dev) (void)hipFree(S->arena_dev);
         if (S->arena_host) (void)hipHostFree(S->arena_host);
         if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
+        if (S->ev_origin) (void)hipEventDestroy(S->ev_origin);
         delete S;
         return rc;
     }
@@ -539,6 +558,7 @@ int wmi_server_submit(wmi_server *S, const wmi_request *req, uint64_t *ticket)
         }
         st->series[r.a].busy++;
         st->series[r.b].busy++;
+        q->pinned = true;
     }
     q->r = r;
     q->pairs = q->nwin * (uint64_t)r.w * (r.w - 1);
@@ -646,6 +666,24 @@ int wmi_server_stats_get(wmi_server *S, wmi_server_stats *out)
         return fail(WMI_EINVAL, "wmi_server_stats_get: null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     *out = S->stats;
+    // union of the launch intervals: device time with at least one launch
+    // of the server in flight (the two slots overlap)
+    std::vector<std::pair<float, float>> iv = S->intervals;
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, cur_s = 0.0, cur_e = -1.0;
+    for (const auto &p : iv) {
+        if (p.first > cur_e) {
+            if (cur_e > cur_s)
+                busy += cur_e - cur_s;
+            cur_s = p.first;
+            cur_e = p.second;
+        } else if (p.second > cur_e) {
+            cur_e = p.second;
+        }
+    }
+    if (cur_e > cur_s)
+        busy += cur_e - cur_s;
+    out->busy_union_us = 1e3 * busy;
     return WMI_OK;
 }
 
@@ -670,8 +708,7 @@ int wmi_server_destroy(wmi_server *S)
     (void)hipStreamSynchronize(S->copy_stream);
     for (auto &kv : S->reqs) {
         Req *r = kv.second;
-        if (r->state != 2)
-            unpin(S, r);
+        unpin(S, r);
         (void)hipEventDestroy(r->ev_copy);
         delete r;
     }
@@ -685,6 +722,7 @@ int wmi_server_destroy(wmi_server *S)
     (void)hipFree(S->arena_dev);
     (void)hipHostFree(S->arena_host);
     (void)hipStreamDestroy(S->copy_stream);
+    (void)hipEventDestroy(S->ev_origin);
     {
         std::lock_guard<std::mutex> lk(st->mu);
         st->servers.erase(S);

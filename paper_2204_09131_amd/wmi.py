@@ -99,7 +99,8 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("requests_done", ctypes.c_uint64), ("windows_done", ctypes.c_uint64),
                 ("ordered_pairs_done", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("busy_us", ctypes.c_double), ("arena_bytes", ctypes.c_uint64),
-                ("arena_peak_bytes", ctypes.c_uint64), ("queued_peak", ctypes.c_uint64)]
+                ("arena_peak_bytes", ctypes.c_uint64), ("queued_peak", ctypes.c_uint64),
+                ("busy_union_us", ctypes.c_double)]
 
 
 class _TdParams(ctypes.Structure):
