@@ -569,6 +569,160 @@ static int query_windows(const wmi_query &q, const std::vector<Series> &ser, uin
     return WMI_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A batch's validated queries, their windows, its work list and the layout
+// of its device buffer (offsets in bytes, 256-byte aligned).
+struct BatchBuild {
+    std::vector<Series> ser;
+    std::vector<uint64_t> wstart;  // windows in query order (a triple: base, extension, union)
+    std::vector<uint32_t> wm, wquery, used;
+    uint64_t pairs = 0, n_win = 0, n_items = 0, n_prep = 0;
+    bool plain = false;
+    Plan plan;
+    std::vector<Item> queue;
+    size_t o_win = 0, o_item = 0, o_qd = 0, o_prep = 0, desc_bytes = 0, o_sorted = 0, o_acc = 0, o_wdone = 0,
+           o_qdone = 0, o_counter = 0, o_wmi = 0, o_wflags = 0, o_ready = 0, o_res = 0, res_bytes = 0,
+           dev_bytes = 0;
+};
+
+int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, BatchBuild &B)
+{
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        B.ser = st->series;
+    }
+    B.wstart.reserve(count);
+    B.wm.reserve(count);
+    B.wquery.reserve(count);
+    for (uint64_t t = 0; t < count; ++t) {
+        uint64_t s3[3];
+        uint32_t m3[3], nw = 0;
+        if (int rc = query_windows(qs[t], B.ser, t, s3, m3, &nw))
+            return rc;
+        for (uint32_t r = 0; r < nw; ++r) {
+            B.wstart.push_back(s3[r]);
+            B.wm.push_back(m3[r]);
+            B.wquery.push_back((uint32_t)t);
+            B.pairs += (uint64_t)m3[r] * (m3[r] - 1);
+        }
+        B.used.push_back(qs[t].a);
+        B.used.push_back(qs[t].b);
+    }
+    B.n_win = B.wm.size();
+    if (B.n_win > 0x7FFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu windows)",
+                    (unsigned long long)B.n_win);
+    std::sort(B.used.begin(), B.used.end());
+    B.used.erase(std::unique(B.used.begin(), B.used.end()), B.used.end());
+
+    // ---- work items ---------------------------------------------------------
+    B.plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
+    plan_items(B.wm, B.wquery, count, B.plain, B.plan);
+    if (!B.plain)
+        plan_queue(B.plan, B.wm, B.queue);
+    B.n_items = B.plain ? B.plan.items.size() : B.queue.size();
+    B.n_prep = B.plan.prep_list.size();
+    if (B.plan.split_pts > 0xFFFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu points in large windows)",
+                    (unsigned long long)B.plan.split_pts);
+
+    // ---- layout -------------------------------------------------------------
+    const size_t A = 256;
+    B.o_win = 0;
+    B.o_item = align_up(B.o_win + B.n_win * sizeof(WinDesc), A);
+    B.o_qd = align_up(B.o_item + B.n_items * sizeof(Item), A);
+    B.o_prep = align_up(B.o_qd + count * sizeof(QDesc), A);
+    B.desc_bytes = align_up(B.o_prep + B.n_prep * sizeof(uint32_t), A);
+    B.o_sorted = B.desc_bytes;
+    B.o_acc = align_up(B.o_sorted + (size_t)kSortedWords * B.plan.split_pts * sizeof(int32_t), A);
+    B.o_wdone = align_up(B.o_acc + B.n_win * sizeof(unsigned long long), A);
+    B.o_qdone = align_up(B.o_wdone + B.n_win * sizeof(uint32_t), A);
+    B.o_counter = align_up(B.o_qdone + count * sizeof(uint32_t), A);
+    B.o_wmi = align_up(B.o_counter + sizeof(uint32_t), A);
+    B.o_wflags = align_up(B.o_wmi + B.n_win * sizeof(double), A);
+    B.o_ready = align_up(B.o_wflags + B.n_win * sizeof(uint32_t), A);
+    B.o_res = align_up(B.o_ready + B.n_win * sizeof(uint32_t), A);
+    // results and the error word are downloaded together
+    B.res_bytes = count * sizeof(Result) + sizeof(uint32_t);
+    B.dev_bytes = align_up(B.o_res + B.res_bytes, A);
+    return WMI_OK;
+}
+
+// Window, item, query and prep-list descriptors into the host image of the
+// descriptor prefix [0, desc_bytes) of the device buffer.
+void write_descriptors(const BatchBuild &B, const wmi_query *qs, uint64_t count, const wmi_params *p, char *host)
+{
+    WinDesc *hw = reinterpret_cast<WinDesc *>(host + B.o_win);
+    Item *hi = reinterpret_cast<Item *>(host + B.o_item);
+    QDesc *hq = reinterpret_cast<QDesc *>(host + B.o_qd);
+    uint32_t *hp = reinterpret_cast<uint32_t *>(host + B.o_prep);
+    for (uint64_t i = 0; i < B.n_win; ++i) {
+        const uint32_t t = B.wquery[i];
+        WinDesc &d = hw[i];
+        d.x = B.ser[qs[t].a].d + B.wstart[i];
+        d.y = B.ser[qs[t].b].d + B.wstart[i];
+        d.m = B.wm[i];
+        d.query = t;
+        d.sorted_off = B.plan.wsorted[i];
+        d.n_items = B.plan.wnitems[i];
+    }
+    for (uint64_t t = 0, i = 0; t < count; ++t) {
+        hq[t].win0 = (uint32_t)i;
+        uint32_t nw = 0;
+        while (i < B.n_win && B.wquery[i] == (uint32_t)t) {
+            ++nw;
+            ++i;
+        }
+        hq[t].nwin = nw;
+        hq[t].tau_eff = p->tau_normalize ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
+    }
+    std::copy(B.plan.prep_list.begin(), B.plan.prep_list.end(), hp);
+    if (B.plain)
+        std::copy(B.plan.items.begin(), B.plan.items.end(), hi);
+    else
+        std::copy(B.queue.begin(), B.queue.end(), hi);
+}
+
+// Launch arguments over a device buffer laid out as B (results to res, the
+// error word to err).
+void set_args(const BatchBuild &B, const wmi_store *st, const wmi_params *p, uint64_t count, char *dev, Result *res,
+              uint32_t *err, LaunchArgs &a)
+{
+    a = LaunchArgs{};
+    a.win = reinterpret_cast<const WinDesc *>(dev + B.o_win);
+    a.item = reinterpret_cast<const Item *>(dev + B.o_item);
+    a.qd = reinterpret_cast<const QDesc *>(dev + B.o_qd);
+    a.sorted = reinterpret_cast<int32_t *>(dev + B.o_sorted);
+    a.acc = reinterpret_cast<unsigned long long *>(dev + B.o_acc);
+    a.wdone = reinterpret_cast<uint32_t *>(dev + B.o_wdone);
+    a.qdone = reinterpret_cast<uint32_t *>(dev + B.o_qdone);
+    a.counter = reinterpret_cast<uint32_t *>(dev + B.o_counter);
+    a.wmi = reinterpret_cast<double *>(dev + B.o_wmi);
+    a.wflags = reinterpret_cast<uint32_t *>(dev + B.o_wflags);
+    a.res = res;
+    a.err = err;
+    a.ready = reinterpret_cast<uint32_t *>(dev + B.o_ready);
+    a.psi_d = st->psi_d;
+    a.psi_fix = st->psi_fix;
+    a.prep_list = reinterpret_cast<const uint32_t *>(dev + B.o_prep);
+    a.n_prep = (uint32_t)B.n_prep;
+    a.n_win = (uint32_t)B.n_win;
+    a.n_items = (uint32_t)B.n_items;
+    a.n_query = (uint32_t)count;
+    a.item_begin = 0;
+    a.k = p->k;
+    a.estimator = p->estimator;
+    a.persistent = 1;
+    a.win_begin = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,
                wmi_batch **out)
 {
@@ -583,79 +737,10 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         return rc;
     DeviceGuard g(st->device);
 
-    // ---- validate and size ------------------------------------------------
-    std::vector<Series> ser;
-    {
-        std::lock_guard<std::mutex> lk(st->mu);
-        ser = st->series;
-    }
-    // windows in query order (a triple: base, extension, union)
-    std::vector<uint64_t> wstart;
-    std::vector<uint32_t> wm, wquery;
-    std::vector<uint32_t> used;
-    uint64_t pairs = 0;
-    wstart.reserve(count);
-    wm.reserve(count);
-    wquery.reserve(count);
-    for (uint64_t t = 0; t < count; ++t) {
-        uint64_t s3[3];
-        uint32_t m3[3], nw = 0;
-        if (int rc = query_windows(qs[t], ser, t, s3, m3, &nw))
-            return rc;
-        for (uint32_t r = 0; r < nw; ++r) {
-            wstart.push_back(s3[r]);
-            wm.push_back(m3[r]);
-            wquery.push_back((uint32_t)t);
-            pairs += (uint64_t)m3[r] * (m3[r] - 1);
-        }
-        used.push_back(qs[t].a);
-        used.push_back(qs[t].b);
-    }
-    const uint64_t n_win = wm.size();
-    if (n_win > 0x7FFFFFF0ull)
-        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu windows)", (unsigned long long)n_win);
-    std::sort(used.begin(), used.end());
-    used.erase(std::unique(used.begin(), used.end()), used.end());
-
-    // ---- work items ---------------------------------------------------------
-    const bool plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
-    Plan plan;
-    plan_items(wm, wquery, count, plain, plan);
-    std::vector<Item> &items = plan.items;
-    std::vector<uint64_t> &cost = plan.cost;
-    std::vector<uint32_t> &prep_list = plan.prep_list, &wsorted = plan.wsorted, &wnitems = plan.wnitems,
-                          &first_item = plan.first_item;
-    std::vector<int32_t> &wprep = plan.wprep;
-    const uint64_t split_pts = plan.split_pts;
-    std::vector<Item> queue;
-    if (!plain)
-        plan_queue(plan, wm, queue);
-    const uint64_t n_items = plain ? items.size() : queue.size();
-    const uint64_t n_prep = prep_list.size();
-    if (split_pts > 0xFFFFFFF0ull)
-        return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu points in large windows)",
-                    (unsigned long long)split_pts);
-
-    // ---- layout -------------------------------------------------------------
-    const size_t A = 256;
-    size_t o_win = 0;
-    size_t o_item = align_up(o_win + n_win * sizeof(WinDesc), A);
-    size_t o_qd = align_up(o_item + n_items * sizeof(Item), A);
-    size_t o_prep = align_up(o_qd + count * sizeof(QDesc), A);
-    size_t desc_bytes = align_up(o_prep + n_prep * sizeof(uint32_t), A);
-    size_t o_sorted = desc_bytes;
-    size_t o_acc = align_up(o_sorted + (size_t)kSortedWords * split_pts * sizeof(int32_t), A);
-    size_t o_wdone = align_up(o_acc + n_win * sizeof(unsigned long long), A);
-    size_t o_qdone = align_up(o_wdone + n_win * sizeof(uint32_t), A);
-    size_t o_counter = align_up(o_qdone + count * sizeof(uint32_t), A);
-    size_t o_wmi = align_up(o_counter + sizeof(uint32_t), A);
-    size_t o_wflags = align_up(o_wmi + n_win * sizeof(double), A);
-    size_t o_ready = align_up(o_wflags + n_win * sizeof(uint32_t), A);
-    size_t o_res = align_up(o_ready + n_win * sizeof(uint32_t), A);
-    // results and the error word are downloaded together
-    size_t res_bytes = count * sizeof(Result) + sizeof(uint32_t);
-    size_t dev_bytes = align_up(o_res + res_bytes, A);
-
+    BatchBuild B;
+    if (int rc = build_batch(st, qs, count, p, B))
+        return rc;
+    const size_t dev_bytes = B.dev_bytes, desc_bytes = B.desc_bytes;
     if (dev_bytes > st->budget)
         return fail(WMI_ENOMEM, "wmi_submit: batch needs %zu bytes of device memory, budget is %llu", dev_bytes,
                     (unsigned long long)st->budget);
@@ -668,7 +753,7 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
             // running batches release their budget from the stream callback
             st->cv.wait(lk, [&] { return st->inflight + dev_bytes <= st->budget; });
         }
-        for (uint32_t id : used)
+        for (uint32_t id : B.used)
             if (id >= st->series.size() || !st->series[id].live)
                 return fail(WMI_EINVAL, "wmi_submit: series %u removed during submit", id);
     }
@@ -677,11 +762,11 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     b->count = count;
     b->params = *p;
     b->stream = stream ? (hipStream_t)stream : st->stream;
-    b->series_used = used;
+    b->series_used = B.used;
     b->dev_bytes = dev_bytes;
     b->desc_bytes = desc_bytes;
-    b->stats.windows = n_win;
-    b->stats.ordered_pairs = pairs;
+    b->stats.windows = B.n_win;
+    b->stats.ordered_pairs = B.pairs;
     {
         std::lock_guard<std::mutex> lk(st->mu);
         hold_locked(b);  // reserve budget and pins until the batch's runs complete
@@ -702,82 +787,29 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     hipError_t e = hipMalloc(&b->dev, dev_bytes);
     if (e != hipSuccess)
         return bail(e, "hipMalloc(batch)");
-    b->host_bytes = desc_bytes + align_up(res_bytes, A);
-    e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, A), hipHostMallocDefault);
+    b->host_bytes = desc_bytes + align_up(B.res_bytes, 256);
+    e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, 256), hipHostMallocDefault);
     if (e != hipSuccess)
         return bail(e, "hipHostMalloc(batch)");
     e = hipEventCreate(&b->ev_end);
     if (e != hipSuccess)
         return bail(e, "hipEventCreate");
 
-    // ---- descriptors --------------------------------------------------------
-    WinDesc *hw = reinterpret_cast<WinDesc *>(b->host + o_win);
-    Item *hi = reinterpret_cast<Item *>(b->host + o_item);
-    QDesc *hq = reinterpret_cast<QDesc *>(b->host + o_qd);
-    uint32_t *hp = reinterpret_cast<uint32_t *>(b->host + o_prep);
+    // ---- descriptors and launch arguments ------------------------------------
+    write_descriptors(B, qs, count, p, b->host);
     b->h_res = reinterpret_cast<Result *>(b->host + desc_bytes);
-    for (uint64_t i = 0; i < n_win; ++i) {
-        const uint32_t t = wquery[i];
-        WinDesc &d = hw[i];
-        d.x = ser[qs[t].a].d + wstart[i];
-        d.y = ser[qs[t].b].d + wstart[i];
-        d.m = wm[i];
-        d.query = t;
-        d.sorted_off = wsorted[i];
-        d.n_items = wnitems[i];
+    if (B.plain) {
+        b->win_first_item = std::move(B.plan.first_item);
+        b->win_prep = std::move(B.plan.wprep);
     }
-    for (uint64_t t = 0, i = 0; t < count; ++t) {
-        hq[t].win0 = (uint32_t)i;
-        uint32_t nw = 0;
-        while (i < n_win && wquery[i] == (uint32_t)t) {
-            ++nw;
-            ++i;
-        }
-        hq[t].nwin = nw;
-        hq[t].tau_eff = p->tau_normalize ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
-    }
-    std::copy(prep_list.begin(), prep_list.end(), hp);
-    if (plain) {
-        b->win_first_item = std::move(first_item);
-        b->win_prep = std::move(wprep);
-        std::copy(items.begin(), items.end(), hi);
-    } else {
-        std::copy(queue.begin(), queue.end(), hi);
-    }
-    (void)cost;
-
-    // ---- launch arguments -----------------------------------------------------
     LaunchArgs &a = b->args;
-    a.win = reinterpret_cast<const WinDesc *>(b->dev + o_win);
-    a.item = reinterpret_cast<const Item *>(b->dev + o_item);
-    a.qd = reinterpret_cast<const QDesc *>(b->dev + o_qd);
-    a.sorted = reinterpret_cast<int32_t *>(b->dev + o_sorted);
-    a.acc = reinterpret_cast<unsigned long long *>(b->dev + o_acc);
-    a.wdone = reinterpret_cast<uint32_t *>(b->dev + o_wdone);
-    a.qdone = reinterpret_cast<uint32_t *>(b->dev + o_qdone);
-    a.counter = reinterpret_cast<uint32_t *>(b->dev + o_counter);
-    a.wmi = reinterpret_cast<double *>(b->dev + o_wmi);
-    a.wflags = reinterpret_cast<uint32_t *>(b->dev + o_wflags);
-    a.res = reinterpret_cast<Result *>(b->dev + o_res);
-    a.err = reinterpret_cast<uint32_t *>(b->dev + o_res + count * sizeof(Result));
-    a.ready = reinterpret_cast<uint32_t *>(b->dev + o_ready);
-    a.psi_d = st->psi_d;
-    a.psi_fix = st->psi_fix;
-    a.prep_list = reinterpret_cast<const uint32_t *>(b->dev + o_prep);
-    a.n_prep = (uint32_t)n_prep;
-    a.n_win = (uint32_t)n_win;
-    a.n_items = (uint32_t)n_items;
-    a.n_query = (uint32_t)count;
-    a.item_begin = 0;
-    a.k = p->k;
-    a.estimator = p->estimator;
-    a.persistent = 1;
-    a.win_begin = 0;
+    set_args(B, st, p, count, b->dev, reinterpret_cast<Result *>(b->dev + B.o_res),
+             reinterpret_cast<uint32_t *>(b->dev + B.o_res + count * sizeof(Result)), a);
     b->d_res = a.res;
     int occ = main_occupancy(p->k);
     uint64_t slots = (uint64_t)st->cu_count * (uint64_t)occ;
-    b->grid = (uint32_t)std::min<uint64_t>(n_items, slots);
-    b->stats.items = (uint32_t)n_items;
+    b->grid = (uint32_t)std::min<uint64_t>(B.n_items, slots);
+    b->stats.items = (uint32_t)B.n_items;
     b->stats.grid = b->grid;
     b->stats.wg_per_cu = (uint32_t)occ;
     b->stats.cus = (uint32_t)st->cu_count;
