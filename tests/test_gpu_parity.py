@@ -169,7 +169,8 @@ def test_config2_all_windows(store, orc, cfg2):
     got = store.evaluate(q, k=4)
     ref = orc.batch(w.series, w.queries, k=4)
     worst = mi_close(got, ref, ("mi_base",))
-    log(f"config2 max |dMI| = {worst:.3e}")
+    assert np.array_equal(got["flags"], ref["flags"])
+    log(f"config2 max |dMI| = {worst:.3e}; flags equal")
 
 
 def test_config2_replay_bit_identical(store, cfg2):
