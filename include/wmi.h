@@ -179,6 +179,29 @@ int wmi_series_length(wmi_store *store, uint32_t id, uint64_t *n);
 int wmi_submit(wmi_store *store, const wmi_query *host_queries, uint64_t count,
                const wmi_params *params, void *stream, wmi_batch **out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as wmi_submit, without allocating.  Descriptors, sorted
+ * marginals, counters and per-window estimates of the call live in a static
+ * device array of WMI_NOALLOC_SCRATCH_BYTES per device, held until the process
+ * ends; results (count entries of 32 bytes, as wmi_read writes them) go to
+ * d_results, device memory the caller owns.  Queries are host memory, read
+ * before return.  Synchronous: returns once the results are in d_results
+ * (work ordered on `stream`, NULL for the store's stream).  No hipMalloc,
+ * hipFree or pinned-host allocation is made; the work list is planned in
+ * ordinary host memory.  Every call on a device shares that device's array
+ * and overwrites it; the library serialises calls per device, so calls that
+ * overlap on one GPU wait for each other.
+ * Errors: as wmi_submit; WMI_EINVAL for params->flags != 0 (no plain form,
+ * no budget); WMI_ENOMEM when the call needs more scratch than the array
+ * holds (about 80 bytes per window, 56 per query and 12 per point of each
+ * window above 512 points).
+ */
+#define WMI_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int wmi_submit_noalloc(wmi_store *store, const wmi_query *host_queries, uint64_t count,
+                       const wmi_params *params, void *stream, wmi_result *d_results);
+
 /* Wait up to timeout_us microseconds (< 0: forever) for a batch to finish.
  * WMI_ETIMEDOUT leaves the batch running. */
 int wmi_wait(wmi_batch *batch, int64_t timeout_us);

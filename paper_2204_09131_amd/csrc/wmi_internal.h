@@ -23,6 +23,7 @@
 // CompactResult records into request slices of the server's arena instead
 // of res.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace wmi {
@@ -42,6 +43,9 @@ constexpr int kLocalSort = 1024;          // windows x pow2(max m) per local ite
 constexpr uint32_t kItemLocal = 0x80000000u;
 constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
+// Device scratch of the allocation-free entry point: one static array per
+// device (descriptors, sorted data, counters, estimates of one call).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 constexpr uint32_t kErrWait = 1u;            // error word: a dependency wait gave up
 // ready word of a split window, written by its prep item once the sorted data
 // is in HBM: kReady, kReadyOffGrid if a value is off the grid, and the key

@@ -47,6 +47,9 @@
 // its ready flag and read after an acquire fence.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "wmi_internal.h"
 
 namespace wmi {
@@ -1749,6 +1752,39 @@ hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s)
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// scratch of the allocation-free entry point
+// --------------------------------------------------------------------------
+// One static array per device, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: it takes the device address
+// from noalloc_scratch(), looked up once per device with that device current.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void **ptr)
+{
+    static std::mutex mu;
+    static std::vector<void *> addr;  // per device ordinal
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0)
+        return hipErrorInvalidDevice;
+    if ((size_t)device >= addr.size())
+        addr.resize((size_t)device + 1, nullptr);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess)
+            return e;
+        if (cur != device)
+            return hipErrorInvalidDevice;  // the caller makes the device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 #endif  // !WMI_MAIN_K
 
 // The main kernel is instantiated once per k, each in its own translation

@@ -353,6 +353,8 @@ int wmi_store_create(const wmi_store_desc *desc, wmi_store **out)
         e = hipMemcpy(st->psi_d, pd.data(), pd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(st->psi_fix, pf.data(), pf.size() * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = noalloc_scratch(st->device, &st->scratch);
     if (e != hipSuccess) {
         int rc = fail(WMI_EHIP, "wmi_store_create: %s", hipGetErrorString(e));
         if (st->psi_d) (void)hipFree(st->psi_d);
@@ -825,6 +827,81 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         return rc;
     }
     *out = b;
+    return WMI_OK;
+}
+
+int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,
+                       wmi_result *d_results)
+{
+    static_assert(WMI_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size");
+    if (!st || !p || (count && (!qs || !d_results)))
+        return fail(WMI_EINVAL, "wmi_submit_noalloc: null argument");
+    if (int rc = validate_params(p))
+        return rc;
+    if (p->flags)
+        return fail(WMI_EINVAL, "wmi_submit_noalloc: flags must be 0");
+    if (count > 0xFFFFFFF0ull)
+        return fail(WMI_EINVAL, "wmi_submit_noalloc: too many queries in one call");
+    if (int rc = check_poison(st))
+        return rc;
+    if (count == 0)
+        return WMI_OK;
+    DeviceGuard g(st->device);
+    if (!st->scratch)
+        return fail(WMI_EHIP, "wmi_submit_noalloc: no scratch address for device %d", st->device);
+    BatchBuild B;
+    if (int rc = build_batch(st, qs, count, p, B))
+        return rc;
+    // descriptors, sorted data, counters and estimates, then the error word
+    const size_t need = B.o_res + sizeof(uint32_t);
+    if (need > kNoAllocScratchBytes)
+        return fail(WMI_ENOMEM,
+                    "wmi_submit_noalloc: the call needs %zu bytes of scratch, the limit is %zu "
+                    "(%llu windows, %llu points in windows above %d points)",
+                    need, kNoAllocScratchBytes, (unsigned long long)B.n_win,
+                    (unsigned long long)B.plan.split_pts, kLocalSlots);
+    // one call at a time per device: every call shares the device's array
+    static std::mutex dev_mu[64];
+    std::lock_guard<std::mutex> call_lk(dev_mu[st->device & 63]);
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        for (uint32_t id : B.used)
+            if (id >= st->series.size() || !st->series[id].live)
+                return fail(WMI_EINVAL, "wmi_submit_noalloc: series %u removed during the call", id);
+        for (uint32_t id : B.used)
+            st->series[id].busy++;
+    }
+    auto unpin = [&]() {
+        std::lock_guard<std::mutex> lk(st->mu);
+        for (uint32_t id : B.used)
+            if (id < st->series.size() && st->series[id].busy)
+                st->series[id].busy--;
+        st->cv.notify_all();
+    };
+    std::vector<char> host(B.desc_bytes);
+    write_descriptors(B, qs, count, p, host.data());
+    char *dev = static_cast<char *>(st->scratch);
+    LaunchArgs a;
+    set_args(B, st, p, count, dev, reinterpret_cast<Result *>(d_results), reinterpret_cast<uint32_t *>(dev + B.o_res),
+             a);
+    const uint32_t grid =
+        (uint32_t)std::min<uint64_t>(B.n_items, (uint64_t)st->cu_count * (uint64_t)main_occupancy(p->k));
+    hipStream_t s = stream ? (hipStream_t)stream : st->stream;
+    uint32_t err = 0;
+    hipError_t e = hipMemcpyAsync(dev, host.data(), B.desc_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_clear(a, s);  // counters, sums, flags and the error word start at zero
+    if (e == hipSuccess)
+        e = launch_main(a, grid, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&err, a.err, sizeof err, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    unpin();
+    if (e != hipSuccess)
+        return poison(st, e, "wmi_submit_noalloc");
+    if (err)
+        return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
     return WMI_OK;
 }
 

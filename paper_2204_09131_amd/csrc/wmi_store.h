@@ -54,6 +54,9 @@ hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, 
 hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_parts, Item *queue, WinDesc *win,
                          QDesc *qd, uint64_t *cdst, hipStream_t s);
 int main_occupancy(uint32_t k);
+// Device address of the allocation-free entry point's scratch array on
+// `device` (which must be current); looked up once per device.
+hipError_t noalloc_scratch(int device, void **ptr);
 void build_psi_tables(int n_max, std::vector<double> &psi_d, std::vector<long long> &psi_fix);
 
 }  // namespace wmi
@@ -67,6 +70,7 @@ struct wmi_store {
     double *psi_d = nullptr;
     long long *psi_fix = nullptr;
     int cu_count = 1;
+    void *scratch = nullptr;  // device address of this device's no-alloc scratch array
     std::mutex mu;
     std::condition_variable cv;
     std::vector<wmi::Series> series;

@@ -49,7 +49,7 @@ WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("m
 # the symbols include/wmi.h declares
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
-           "wmi_submit", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
+           "wmi_submit", "wmi_submit_noalloc", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
            "wmi_batch_stats_get", "wmi_batch_count_evals", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
            "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
@@ -149,6 +149,7 @@ def lib():
         "wmi_series_remove": ([vp, u32], ctypes.c_int),
         "wmi_series_length": ([vp, u32, P(u64)], ctypes.c_int),
         "wmi_submit": ([vp, vp, u64, P(_Params), vp, P(vp)], ctypes.c_int),
+        "wmi_submit_noalloc": ([vp, vp, u64, P(_Params), vp, vp], ctypes.c_int),
         "wmi_wait": ([vp, i64], ctypes.c_int),
         "wmi_done": ([vp], ctypes.c_int),
         "wmi_read": ([vp, vp], ctypes.c_int),
@@ -349,6 +350,15 @@ class Store:
             out.append(self.submit(q[i:j], **kw))
             i = j
         return out
+
+    def submit_noalloc(self, queries, d_results: int, k: int = 4, estimator: int = 0, tau: float = 0.0,
+                       tau_normalize: int = 0, stream=None):
+        """wmi_submit_noalloc: results (32 bytes per query) written to the
+        device address d_results; returns once they are there."""
+        q = as_queries(queries)
+        p = _params(k, estimator, tau, tau_normalize, 0)
+        _check(lib().wmi_submit_noalloc(self.h, q.ctypes.data if len(q) else None, len(q), ctypes.byref(p),
+                                        _stream_handle(stream), int(d_results) if d_results else None))
 
     def evaluate(self, queries, **kw) -> np.ndarray:
         b = self.submit(queries, **kw)
