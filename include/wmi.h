@@ -61,6 +61,11 @@ extern "C" {
 /* ---- submit flags (wmi_params.flags) ---------------------------------------- */
 #define WMI_SUBMIT_NONBLOCKING 1u /* WMI_EBUSY instead of waiting for memory  */
 #define WMI_SUBMIT_PLAIN 2u       /* one kernel launch per window (baseline)   */
+/* Evaluate every window on its own, without the reuse of the default batched
+ * form (Section 7.1.2's incremental computation: a noise triple's base and
+ * extension lists come from its union's scan, so a triple costs its union's
+ * distances only).  Results are identical; for comparison. */
+#define WMI_SUBMIT_NO_REUSE 4u
 
 typedef struct wmi_store wmi_store;
 typedef struct wmi_batch wmi_batch;

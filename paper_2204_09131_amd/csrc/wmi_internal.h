@@ -4,10 +4,11 @@
 //   WinDesc  win[W]      one per window (a noise triple contributes three)
 //   Item     item[I]     the work queue: prep items first (sort a split
 //                        window's marginals), then split items (one block of
-//                        query points of a window above kLocalSlots points)
-//                        and local items (up to kLocalWindows consecutive
-//                        windows done entirely inside one workgroup), larger
-//                        work first
+//                        query points of a window above kLocalSlots points),
+//                        local items (up to kLocalWindows consecutive
+//                        windows done entirely inside one workgroup) and
+//                        triple items (up to kTripleMax noise triples, each
+//                        evaluated through its union), larger work first
 //   u32      prep[Np]    the split windows (plain form: sorted by the prep
 //                        kernel, one launch per window)
 //   u32      ready[W]    per window: sorted marginals written
@@ -42,6 +43,8 @@ constexpr int kLocalWindows = 16;         // windows per local item
 constexpr int kLocalSort = 1024;          // windows x pow2(max m) per local item
 constexpr uint32_t kItemLocal = 0x80000000u;
 constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
+constexpr uint32_t kItemTriple = 0x20000000u;  // noise triples evaluated through their unions
+constexpr int kTripleMax = 5;                   // triples per triple item
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
 // Device scratch of the allocation-free entry point: one static array per
 // device (descriptors, sorted data, counters, estimates of one call).
@@ -71,7 +74,8 @@ struct WinDesc {            // 32 bytes
 
 struct Item {               // 8 bytes
     uint32_t win;           // split / prep: the window; local: its first window
-    uint32_t info;          // split: first query point; local: kItemLocal | windows; prep: kItemPrep
+    uint32_t info;          // split: first query point; local: kItemLocal | windows; prep: kItemPrep;
+                            // triple: kItemTriple | triples (win: the first triple's base window)
 };
 
 struct QDesc {              // 16 bytes

@@ -13,8 +13,12 @@
 // counter; the queue holds prep items, then local items, then split items,
 // then the cheapest local items (the host's plan decides the order):
 //
+//   triple item up to 5 noise triples of at most 512 union points in all:
+//               each point's base or extension list and its union list
+//               come from one scan over the union, so a triple costs the
+//               distances of its union only.
 //   local item  up to 16 consecutive windows of at most 512 points in total
-//               (whole queries, noise triples included, where they fit).
+//               (whole queries where they fit).
 //               One workgroup stages them in LDS, finds every point's
 //               neighbours (all pairs), sorts each window's marginals in LDS
 //               (bitonic), counts by binary search, sums digamma terms with
@@ -1568,6 +1572,423 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 }
 
 // --------------------------------------------------------------------------
+// triple items: noise triples evaluated through their union
+// --------------------------------------------------------------------------
+// The base w_o and the extension w_d of a noise triple partition its union
+// w'' (Definition 6.2 as applied in Section 6.2).  A point's k nearest
+// neighbours inside its own part are the k smallest keys among that part's
+// candidates, and the k smallest of a set do not depend on the order they
+// are inserted in, so one scan over the union gives both of a point's lists:
+// the base's candidates first, after which a base point's list is its base
+// list (kept), then the extension's, which complete every union list and,
+// inserted into a second list, give an extension point its extension list.
+// A triple costs the distances of its union only.
+//
+// Counts inside a part: with S the smaller part, a point of S counts over S
+// by brute force; a point of the other part counts over the union (binary
+// searches in the sorted union marginals, as the union's own counts) and
+// subtracts its count over S.  Up to kTripleMax triples (whole queries) with
+// at most kLocalSlots union points in total share a workgroup.
+
+struct TripleShared {
+    const float *x[kTripleMax];
+    const float *y[kTripleMax];
+    uint32_t off[kTripleMax + 1];             // first slot of each union (even)
+    uint32_t m[kTripleMax];                   // union points
+    uint32_t a0[kTripleMax], na[kTripleMax];  // base part [a0, a0 + na) of the union
+    uint32_t b0[kTripleMax], nb[kTripleMax];  // extension part [b0, b0 + nb)
+    uint32_t bits[kTripleMax];                // index bits of 32-bit keys; 0: 64-bit keys
+    uint32_t flags[kTripleMax];
+    int32_t mn[2][kTripleMax];
+    int32_t mx[2][kTripleMax];
+    unsigned long long acc[kTripleMax][3];    // base, extension, union
+    uint32_t P, log2P;
+};
+
+// Scan candidates j = j0 + jj, jj in [0, n), of a thread's union (cw: its
+// keys, two words per point) for the thread's two query points into the
+// S-entry union lists u0, u1; with PART the keys also enter the part lists
+// p0, p1 of the queries whose in0 / in1 is set.  MASK: jj >= n_lane is past
+// this lane's range (the wave's loop runs to its longest range) and j0 is
+// per lane; otherwise j0 and n are wave-uniform.
+template <int S, bool MASK, bool PART>
+__device__ __forceinline__ void trip_scan(const uint32_t *__restrict__ cw, int j0, int n, int n_lane, uint32_t qx0,
+                                          uint32_t qy0, uint32_t qx1, uint32_t qy1, bool in0, bool in1,
+                                          uint32_t (&u0)[S], uint32_t (&u1)[S], uint32_t (&p0)[S], uint32_t (&p1)[S])
+{
+    const uint2 *c2 = reinterpret_cast<const uint2 *>(cw);
+    const int jlast = j0 + n_lane - 1;  // MASK: reads past the lane's range stay on its last candidate
+    int jj = 0;
+    for (; jj + 4 <= n; jj += 4) {
+        uint2 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            c[u] = c2[MASK ? min(j0 + jj + u, jlast) : j0 + jj + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t j = (uint32_t)(j0 + jj + u);
+            uint32_t k0, k1;
+            if (MASK) {
+                k0 = tmax(sad_key_v(qx0, c[u].x, j), sad_key_v(qy0, c[u].y, j));
+                k1 = tmax(sad_key_v(qx1, c[u].x, j), sad_key_v(qy1, c[u].y, j));
+                k0 = jj + u < n_lane ? k0 : 0xFFFFFFFFu;
+                k1 = jj + u < n_lane ? k1 : 0xFFFFFFFFu;
+            } else {
+                k0 = tmax(sad_key(qx0, c[u].x, j), sad_key(qy0, c[u].y, j));
+                k1 = tmax(sad_key(qx1, c[u].x, j), sad_key(qy1, c[u].y, j));
+            }
+            insert_sorted<S>(u0, k0);
+            insert_sorted<S>(u1, k1);
+            if (PART) {
+                insert_sorted<S>(p0, in0 ? k0 : 0xFFFFFFFFu);
+                insert_sorted<S>(p1, in1 ? k1 : 0xFFFFFFFFu);
+            }
+        }
+    }
+    for (; jj < n; ++jj) {
+        const uint2 c = c2[MASK ? min(j0 + jj, jlast) : j0 + jj];
+        const uint32_t j = (uint32_t)(j0 + jj);
+        uint32_t k0, k1;
+        if (MASK) {
+            k0 = tmax(sad_key_v(qx0, c.x, j), sad_key_v(qy0, c.y, j));
+            k1 = tmax(sad_key_v(qx1, c.x, j), sad_key_v(qy1, c.y, j));
+            k0 = jj < n_lane ? k0 : 0xFFFFFFFFu;
+            k1 = jj < n_lane ? k1 : 0xFFFFFFFFu;
+        } else {
+            k0 = tmax(sad_key(qx0, c.x, j), sad_key(qy0, c.y, j));
+            k1 = tmax(sad_key(qx1, c.x, j), sad_key(qy1, c.y, j));
+        }
+        insert_sorted<S>(u0, k0);
+        insert_sorted<S>(u1, k1);
+        if (PART) {
+            insert_sorted<S>(p0, in0 ? k0 : 0xFFFFFFFFu);
+            insert_sorted<S>(p1, in1 ? k1 : 0xFFFFFFFFu);
+        }
+    }
+}
+
+// The same with 64-bit keys (d << 12 | j), one query point, for unions whose
+// value range does not fit 32-bit keys.
+template <int S>
+__device__ __forceinline__ void trip_scan_wide(const uint32_t *__restrict__ cw, int j0, int n, uint32_t qx, uint32_t qy,
+                                               bool in, bool part, unsigned long long (&u)[S],
+                                               unsigned long long (&p)[S])
+{
+    for (int jj = 0; jj < n; ++jj) {
+        const uint32_t j = (uint32_t)(j0 + jj);
+        const uint32_t d = tmax(sad_u32(qx, cw[2 * j], 0u), sad_u32(qy, cw[2 * j + 1], 0u));
+        const unsigned long long key = ((unsigned long long)d << 12) | (unsigned long long)j;
+        insert_sorted<S>(u, key);
+        if (part)
+            insert_sorted<S>(p, in ? key : ~0ull);
+    }
+}
+
+// #{j in [s0, s0 + ns) of the union : |c_i - c_j| <= e} (estimator 0) or
+// < e (estimator 1) in both coordinates, from the union's keys (key units:
+// coordinates shifted left by the index bits, e likewise).
+__device__ __forceinline__ void trip_count_part(const uint32_t *__restrict__ cw, int s0, int ns, uint32_t qx,
+                                                uint32_t qy, uint32_t ex, uint32_t ey, uint32_t est, int &cx, int &cy)
+{
+    int nx = 0, ny = 0;
+    for (int j = s0; j < s0 + ns; ++j) {
+        const uint32_t dx = sad_u32(qx, cw[2 * j], 0u), dy = sad_u32(qy, cw[2 * j + 1], 0u);
+        nx += est == 0 ? (dx <= ex) : (dx < ex);
+        ny += est == 0 ? (dy <= ey) : (dy < ey);
+    }
+    cx = nx;
+    cy = ny;
+}
+
+template <int K>
+__device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, uint32_t *buf, TripleShared &T)
+{
+    constexpr int S = K + 1;
+    const int tid = threadIdx.x;
+    uint32_t *cand = buf;                                          // keys, two words per union point
+    int32_t *srt_x = reinterpret_cast<int32_t *>(buf + 2 * 1024);  // sorted union marginals
+    int32_t *srt_y = srt_x + kLocalSort;
+
+    if (tid < (int)ntrip) {
+        const uint32_t wb = w0 + 3u * (uint32_t)tid;  // base, extension, union
+        const WinDesc db = a.win[wb], de = a.win[wb + 1], du = a.win[wb + 2];
+        T.x[tid] = du.x;
+        T.y[tid] = du.y;
+        T.m[tid] = du.m;
+        T.a0[tid] = (uint32_t)(db.x - du.x);
+        T.na[tid] = db.m;
+        T.b0[tid] = (uint32_t)(de.x - du.x);
+        T.nb[tid] = de.m;
+        T.flags[tid] = 0u;
+        T.mn[0][tid] = INT32_MAX;
+        T.mn[1][tid] = INT32_MAX;
+        T.mx[0][tid] = INT32_MIN;
+        T.mx[1][tid] = INT32_MIN;
+        for (int r = 0; r < 3; ++r)
+            T.acc[tid][r] = 0ull;
+    }
+    block_sync();
+    if (tid == 0) {
+        uint32_t off = 0, mmax = 2;
+        for (uint32_t t = 0; t < ntrip; ++t) {
+            T.off[t] = off;
+            off += (T.m[t] + 1u) & ~1u;
+            mmax = max(mmax, T.m[t]);
+        }
+        T.off[ntrip] = off;
+        const uint32_t lp = ceil_log2(mmax);
+        T.P = 1u << lp;
+        T.log2P = lp;
+    }
+    block_sync();
+    const uint32_t total = T.off[ntrip];
+    const uint32_t P = T.P, lp = T.log2P;
+
+    // ---- stage: grid integers into the sort segments, per-union extrema
+    int32_t X[2], Y[2];
+    uint32_t W[2];
+    int I[2];
+    bool act[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t s = 2u * (uint32_t)tid + (uint32_t)q;
+        uint32_t t = 0;
+        while (t + 1 < ntrip && T.off[t + 1] <= s)
+            ++t;
+        const int i = (int)s - (int)T.off[t];
+        act[q] = s < total && i < (int)T.m[t];
+        W[q] = t;
+        I[q] = act[q] ? i : 0;
+        X[q] = 0;
+        Y[q] = 0;
+        if (act[q]) {
+            uint32_t off = 0;
+            X[q] = grid_int(T.x[t][i], off);
+            Y[q] = grid_int(T.y[t][i], off);
+            srt_x[(t << lp) + i] = X[q];
+            srt_y[(t << lp) + i] = Y[q];
+            atomicMin(&T.mn[0][t], X[q]);
+            atomicMax(&T.mx[0][t], X[q]);
+            atomicMin(&T.mn[1][t], Y[q]);
+            atomicMax(&T.mx[1][t], Y[q]);
+            if (off)
+                atomicOr(&T.flags[t], kFlagOffGrid);
+        }
+    }
+    for (uint32_t e = tid; e < (ntrip << lp); e += kBlock) {
+        const uint32_t t = e >> lp, i = e & (P - 1u);
+        if (i >= T.m[t]) {
+            srt_x[e] = INT32_MAX;
+            srt_y[e] = INT32_MAX;
+        }
+    }
+    block_sync();
+    if (tid < (int)ntrip) {
+        const uint32_t m = T.m[tid];
+        const uint32_t nb = ceil_log2(m > 1 ? m : 2u);
+        const uint32_t rxr = (uint32_t)(T.mx[0][tid] - T.mn[0][tid]);
+        const uint32_t ryr = (uint32_t)(T.mx[1][tid] - T.mn[1][tid]);
+        T.bits[tid] = (((rxr | ryr) >> (32 - nb)) == 0u) ? nb : 0u;
+    }
+    block_sync();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (act[q]) {
+            const uint32_t s = 2u * (uint32_t)tid + (uint32_t)q;
+            const uint32_t t = W[q], nb = T.bits[t];
+            cand[2 * s] = (uint32_t)(X[q] - T.mn[0][t]) << nb;
+            cand[2 * s + 1] = (uint32_t)(Y[q] - T.mn[1][t]) << nb;
+        }
+    }
+    block_sync();
+
+    // ---- neighbours: union and part lists of both slots in one scan
+    const uint32_t t = W[0];
+    const int m = (int)T.m[t];
+    const bool live = act[0] && m > K;
+    const uint32_t base = T.off[t];
+    const uint32_t *cw = cand + 2 * base;
+    const int a0 = (int)T.a0[t], na = (int)T.na[t], b0 = (int)T.b0[t], nbp = (int)T.nb[t];
+    const bool inA0 = I[0] >= a0 && I[0] < a0 + na, inA1 = I[0] + 1 >= a0 && I[0] + 1 < a0 + na;
+    const uint32_t bits = T.bits[t];
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t RXu[2] = {0u, 0u}, RYu[2] = {0u, 0u}, RXp[2] = {0u, 0u}, RYp[2] = {0u, 0u};
+    {
+        const unsigned long long bal = __ballot(live);
+        if (bal != 0ull) {  // wave-uniform
+            // lanes without a live slot follow the first live lane's union
+            const int first = __ffsll((long long)bal) - 1;
+            const uint32_t tl = live ? t : (uint32_t)__shfl((int)t, first, 64);
+            const int ml = (int)T.m[tl], a0l = (int)T.a0[tl], nal = (int)T.na[tl];
+            const int b0l = (int)T.b0[tl], nbl = (int)T.nb[tl];
+            const uint32_t bitsl = T.bits[tl];
+            const uint32_t *cwl = cand + 2 * T.off[tl];
+            const int il = live ? I[0] : __shfl(I[0], first, 64);
+            // one shape in the whole wave (every triple of the wave alike)?
+            int v_min[5] = {ml, a0l, nal, b0l, nbl}, v_max[5] = {ml, a0l, nal, b0l, nbl};
+            uint32_t bits_min = bitsl;
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    v_min[r] = min(v_min[r], __shfl_xor(v_min[r], o, 64));
+                    v_max[r] = max(v_max[r], __shfl_xor(v_max[r], o, 64));
+                }
+                bits_min = min(bits_min, (uint32_t)__shfl_xor((int)bits_min, o, 64));
+            }
+            bool uniform = true;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                uniform = uniform && v_min[r] == v_max[r];
+            const int mode = __builtin_amdgcn_readfirstlane(bits_min == 0u ? 2 : (uniform ? 0 : 1));
+            const bool in0 = il >= a0l && il < a0l + nal, in1 = il + 1 >= a0l && il + 1 < a0l + nal;
+            const uint32_t maskl = (1u << bitsl) - 1u;
+            if (mode != 2) {
+                const uint32_t qx0 = cwl[2 * il], qy0 = cwl[2 * il + 1];
+                const uint32_t qx1 = cwl[2 * il + 2], qy1 = cwl[2 * il + 3];
+                uint32_t u0[S], u1[S], p0[S], p1[S];
+#pragma unroll
+                for (int r = 0; r < S; ++r)
+                    u0[r] = u1[r] = p0[r] = p1[r] = 0xFFFFFFFFu;
+                if (mode == 0) {
+                    const int A0 = __builtin_amdgcn_readfirstlane(a0l), NA = __builtin_amdgcn_readfirstlane(nal);
+                    const int B0 = __builtin_amdgcn_readfirstlane(b0l), NB = __builtin_amdgcn_readfirstlane(nbl);
+                    trip_scan<S, false, false>(cwl, A0, NA, NA, qx0, qy0, qx1, qy1, false, false, u0, u1, p0, p1);
+#pragma unroll
+                    for (int r = 0; r < S; ++r) {
+                        p0[r] = in0 ? u0[r] : 0xFFFFFFFFu;
+                        p1[r] = in1 ? u1[r] : 0xFFFFFFFFu;
+                    }
+                    trip_scan<S, false, true>(cwl, B0, NB, NB, qx0, qy0, qx1, qy1, !in0, !in1, u0, u1, p0, p1);
+                } else {
+                    trip_scan<S, true, false>(cwl, a0l, v_max[2], nal, qx0, qy0, qx1, qy1, false, false, u0, u1, p0,
+                                              p1);
+#pragma unroll
+                    for (int r = 0; r < S; ++r) {
+                        p0[r] = in0 ? u0[r] : 0xFFFFFFFFu;
+                        p1[r] = in1 ? u1[r] : 0xFFFFFFFFu;
+                    }
+                    trip_scan<S, true, true>(cwl, b0l, v_max[4], nbl, qx0, qy0, qx1, qy1, !in0, !in1, u0, u1, p0, p1);
+                }
+                const uint32_t bb = T.off[tl];
+                radii_from_keys<K, uint32_t>(u0, (uint32_t)il, (int)bitsl, maskl, ml, cand, bb, qx0, qy0, (int)bitsl,
+                                             a.estimator, RXu[0], RYu[0]);
+                radii_from_keys<K, uint32_t>(u1, (uint32_t)il + 1u, (int)bitsl, maskl, ml, cand, bb, qx1, qy1,
+                                             (int)bitsl, a.estimator, RXu[1], RYu[1]);
+                radii_from_keys<K, uint32_t>(p0, (uint32_t)il, (int)bitsl, maskl, ml, cand, bb, qx0, qy0, (int)bitsl,
+                                             a.estimator, RXp[0], RYp[0]);
+                radii_from_keys<K, uint32_t>(p1, (uint32_t)il + 1u, (int)bitsl, maskl, ml, cand, bb, qx1, qy1,
+                                             (int)bitsl, a.estimator, RXp[1], RYp[1]);
+            } else {
+                // some union of the wave needs 64-bit keys: one slot at a time
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int i = il + q;
+                    const bool inq = q == 0 ? in0 : in1;
+                    unsigned long long u[S], p[S];
+#pragma unroll
+                    for (int r = 0; r < S; ++r)
+                        u[r] = p[r] = ~0ull;
+                    const uint32_t qx = cwl[2 * i], qy = cwl[2 * i + 1];
+                    trip_scan_wide<S>(cwl, a0l, nal, qx, qy, false, false, u, p);
+#pragma unroll
+                    for (int r = 0; r < S; ++r)
+                        p[r] = inq ? u[r] : ~0ull;
+                    trip_scan_wide<S>(cwl, b0l, nbl, qx, qy, !inq, true, u, p);
+                    const uint32_t bb = T.off[tl];
+                    radii_from_keys<K, unsigned long long>(u, (unsigned long long)i, 12, 0xFFFu, ml, cand, bb, qx, qy,
+                                                           (int)bitsl, a.estimator, RXu[q], RYu[q]);
+                    radii_from_keys<K, unsigned long long>(p, (unsigned long long)i, 12, 0xFFFu, ml, cand, bb, qx, qy,
+                                                           (int)bitsl, a.estimator, RXp[q], RYp[q]);
+                }
+            }
+            count_evals_lanes(a, live ? (uint32_t)(ml - 1) * (act[1] ? 2u : 1u) : 0u);
+        }
+    }
+    block_sync();
+
+    // ---- sort every union's marginals (segments of P, padded with INT32_MAX)
+    bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, ntrip << lp, P);
+
+    // ---- counts and digamma terms
+    if (live) {
+        const int32_t *sx = srt_x + (t << lp), *sy = srt_y + (t << lp);
+        // the smaller part, counted by brute force
+        const bool small_a = na <= nbp;
+        const int s0 = small_a ? a0 : b0, ns = small_a ? na : nbp;
+        int32_t vx[8], vy[8];
+        int cx[8], cy[8];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            count_bounds(a.estimator, X[q], Y[q], (int32_t)RXu[q], (int32_t)RYu[q], vx + 4 * q, vy + 4 * q);
+            count_bounds(a.estimator, X[q], Y[q], (int32_t)RXp[q], (int32_t)RYp[q], vx + 4 * q + 2, vy + 4 * q + 2);
+        }
+        count_lt_xy<8>(sx, sy, m, vx, vy, cx, cy);
+        long long tu = 0, tpa = 0, tpb = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (!act[q])
+                continue;
+            const int i = I[0] + q;
+            const bool inA = q == 0 ? inA0 : inA1;
+            const bool in_small = small_a ? inA : !inA;
+            const int part_m = inA ? na : nbp;
+            int ux, uy;
+            tu += point_terms(a, cx[4 * q], cx[4 * q + 1], cy[4 * q], cy[4 * q + 1], (int32_t)RXu[q], ux, uy);
+            if (part_m > K) {
+                int sx_n, sy_n;
+                trip_count_part(cw, s0, ns, cw[2 * i], cw[2 * i + 1], RXp[q] << bits, RYp[q] << bits, a.estimator,
+                                sx_n, sy_n);
+                int nx, ny;
+                if (a.estimator == 0) {
+                    nx = in_small ? sx_n - 1 : (cx[4 * q + 2] - cx[4 * q + 3] - 1) - sx_n;
+                    ny = in_small ? sy_n - 1 : (cy[4 * q + 2] - cy[4 * q + 3] - 1) - sy_n;
+                    const long long v = a.psi_fix[nx] + a.psi_fix[ny];
+                    tpa += inA ? v : 0;
+                    tpb += inA ? 0 : v;
+                } else {
+                    const bool pos = RXp[q] > 0u;
+                    nx = !pos ? 0 : (in_small ? sx_n - 1 : (cx[4 * q + 2] - cx[4 * q + 3] - 1) - sx_n);
+                    ny = !pos ? 0 : (in_small ? sy_n - 1 : (cy[4 * q + 2] - cy[4 * q + 3] - 1) - sy_n);
+                    const long long v = a.psi_fix[nx + 1] + a.psi_fix[ny + 1];
+                    tpa += inA ? v : 0;
+                    tpb += inA ? 0 : v;
+                }
+            }
+        }
+        atomicAdd(&T.acc[t][2], (unsigned long long)tu);
+        if (tpa)
+            atomicAdd(&T.acc[t][0], (unsigned long long)tpa);
+        if (tpb)
+            atomicAdd(&T.acc[t][1], (unsigned long long)tpb);
+    }
+    block_sync();
+
+    // ---- estimates of the three windows, then the query's result
+    if (tid < (int)ntrip) {
+        const uint32_t mw[3] = {T.na[tid], T.nb[tid], T.m[tid]};
+        const uint32_t wb = w0 + 3u * (uint32_t)tid;
+        double mi3[3];
+        uint32_t f3[3];
+        for (int r = 0; r < 3; ++r) {
+            uint32_t fl = T.flags[tid];
+            double mi;
+            if ((int)mw[r] <= K) {
+                mi = __builtin_nan("");
+                fl |= kFlagTooShort;
+            } else {
+                mi = window_estimate<K>(a, (int)mw[r], (long long)T.acc[tid][r]);
+            }
+            mi3[r] = mi;
+            f3[r] = fl;
+            a.wmi[wb + r] = mi;
+            a.wflags[wb + r] = fl;
+        }
+        const uint32_t q = a.win[wb].query;
+        store_result(a, q, compose_result(a.qd[q], mi3, f3));
+    }
+}
+
+// --------------------------------------------------------------------------
 // main: persistent loop over items
 // --------------------------------------------------------------------------
 template <int K>
@@ -1575,6 +1996,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
 {
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
+    __shared__ TripleShared T;
     __shared__ long long s_part[kBlock / 64];
     __shared__ int32_t s_red[5];
     __shared__ uint32_t s_cnt[64];
@@ -1598,7 +2020,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
         if (it >= a.n_items)
             break;
         const Item itm = a.item[a.item_begin + it];
-        if (itm.info & kItemLocal) {
+        if (itm.info & kItemTriple) {
+            triple_item<K>(a, itm.win, itm.info & 0xFFu, buf, T);
+        } else if (itm.info & kItemLocal) {
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
         } else if (itm.info & kItemPrep) {
             // a sort that split items of the window will wait for: its waves

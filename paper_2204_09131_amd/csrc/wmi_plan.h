@@ -39,9 +39,14 @@ inline uint32_t plan_pow2(uint32_t v)
 }
 
 // wm[w]: points of window w; wquery[w]: its query (non-decreasing, every query
-// in [0, count) present).
+// in [0, count) present).  A query of three windows is a noise triple (base,
+// extension, union); with fuse_triples (batched form only) triples whose
+// union has at most kLocalSlots points go to triple items: consecutive
+// triples, up to kTripleMax of them, kLocalSlots union points (each padded
+// to even) and kLocalSort sort entries (triples x the power of two at or
+// above the largest union).
 inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wquery, uint64_t count,
-                       bool plain, Plan &out)
+                       bool plain, Plan &out, bool fuse_triples = true)
 {
     const uint64_t n_win = wm.size();
     out = Plan();
@@ -75,12 +80,40 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         }
         cur = Cur();
     };
+    Cur tri;  // the open triple item: n triples from window start
+    auto fits_tri = [](const Cur &c, uint32_t mu) {
+        uint32_t maxm = std::max(std::max(c.maxm, mu), 2u);
+        return c.n + 1 <= (uint32_t)kTripleMax && c.slots + ((mu + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
+               (c.n + 1) * plan_pow2(maxm) <= (uint32_t)kLocalSort;
+    };
+    auto close_tri = [&]() {
+        if (tri.n) {
+            out.items.push_back(Item{tri.start, kItemTriple | tri.n});
+            out.cost.push_back(tri.cost);
+        }
+        tri = Cur();
+    };
     uint32_t w = 0;
     for (uint64_t t = 0; t < count; ++t) {
         const uint32_t w0 = w;
         uint32_t nw = 0;
         while (w0 + nw < n_win && wquery[w0 + nw] == (uint32_t)t)
             ++nw;
+        if (!plain && fuse_triples && nw == 3 && wm[w0 + 2] <= (uint32_t)kLocalSlots) {
+            close();  // a local item holds consecutive windows only
+            const uint32_t mu = wm[w0 + 2];
+            if (!fits_tri(tri, mu))
+                close_tri();
+            if (tri.n == 0)
+                tri.start = w0;
+            tri.n++;
+            tri.slots += (mu + 1u) & ~1u;
+            tri.maxm = std::max(tri.maxm, mu);
+            tri.cost += (uint64_t)mu * mu + 4096u;
+            w += 3;
+            continue;
+        }
+        close_tri();
         if (!plain) {
             // start a fresh item rather than cut a query that fits in one
             bool all_local = true, whole = true;
@@ -131,6 +164,7 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         }
     }
     close();
+    close_tri();
     if (plain)
         out.first_item.push_back((uint32_t)out.items.size());
 }
@@ -162,7 +196,7 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
         std::vector<uint32_t> cnt(66, 0);
         std::vector<size_t> idx;
         for (size_t i = 0; i < P.items.size(); ++i) {
-            const bool local = (P.items[i].info & kItemLocal) != 0;
+            const bool local = (P.items[i].info & (kItemLocal | kItemTriple)) != 0;
             const int ph = local ? (P.cost[i] < kTailCost ? 2 : 0) : 1;
             if (ph == phase) {
                 cnt[bucket(P.cost[i]) + 1]++;

@@ -517,7 +517,7 @@ static int validate_params(const wmi_params *p)
         return fail(WMI_EINVAL, "estimator %u unknown (0 or 1)", p->estimator);
     if (p->tau_normalize > 1)
         return fail(WMI_EINVAL, "tau_normalize must be 0 or 1");
-    if (p->flags & ~(WMI_SUBMIT_NONBLOCKING | WMI_SUBMIT_PLAIN))
+    if (p->flags & ~(WMI_SUBMIT_NONBLOCKING | WMI_SUBMIT_PLAIN | WMI_SUBMIT_NO_REUSE))
         return fail(WMI_EINVAL, "unknown submit flags 0x%x", p->flags);
     if (!std::isfinite(p->tau))
         return fail(WMI_EINVAL, "tau must be finite");
@@ -622,7 +622,7 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
 
     // ---- work items ---------------------------------------------------------
     B.plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
-    plan_items(B.wm, B.wquery, count, B.plain, B.plan);
+    plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE));
     if (!B.plain)
         plan_queue(B.plan, B.wm, B.queue);
     B.n_items = B.plain ? B.plan.items.size() : B.queue.size();

@@ -34,6 +34,7 @@ F_OFFGRID = 8
 STORE_STRICT_GRID = 1
 SUBMIT_NONBLOCKING = 1
 SUBMIT_PLAIN = 2
+SUBMIT_NO_REUSE = 4
 MAX_WINDOW = 4096
 MAX_K = 16
 
@@ -327,9 +328,11 @@ class Store:
         return n.value
 
     def submit(self, queries, k: int = 4, estimator: int = 0, tau: float = 0.0, tau_normalize: int = 0,
-               plain: bool = False, nonblocking: bool = False, stream=None) -> Batch:
+               plain: bool = False, nonblocking: bool = False, no_reuse: bool = False,
+               stream=None) -> Batch:
         q = as_queries(queries)
-        flags = (SUBMIT_PLAIN if plain else 0) | (SUBMIT_NONBLOCKING if nonblocking else 0)
+        flags = ((SUBMIT_PLAIN if plain else 0) | (SUBMIT_NONBLOCKING if nonblocking else 0)
+                 | (SUBMIT_NO_REUSE if no_reuse else 0))
         p = _params(k, estimator, tau, tau_normalize, flags)
         h = ctypes.c_void_p()
         _check(lib().wmi_submit(self.h, q.ctypes.data if len(q) else None, len(q), ctypes.byref(p),

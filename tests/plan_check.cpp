@@ -18,10 +18,11 @@ static int fail(const char *what, long a, long b)
     return 1;
 }
 
-static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wq, uint64_t count, bool plain)
+static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wq, uint64_t count, bool plain,
+                 bool fuse)
 {
     Plan P;
-    plan_items(wm, wq, count, plain, P);
+    plan_items(wm, wq, count, plain, P, fuse);
     const size_t n = wm.size();
     if (P.items.size() != P.cost.size())
         return fail("cost size", (long)P.items.size(), (long)P.cost.size());
@@ -29,7 +30,38 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
     std::vector<std::vector<uint32_t>> split_q0(n);
     for (size_t it = 0; it < P.items.size(); ++it) {
         const Item &I = P.items[it];
-        if (I.info & kItemLocal) {
+        if (I.info & kItemTriple) {
+            // whole noise triples (base, extension, union of one query), the
+            // union within the limits of the kernel's LDS layout
+            const uint32_t nt = I.info & 0xFFu;
+            uint32_t slots = 0, maxm = 2;
+            if (plain || !fuse)
+                return fail("triple item without fusing", (long)it, (long)nt);
+            if (nt < 1 || nt > (uint32_t)kTripleMax || (I.info & 0x1FFFFF00u))
+                return fail("triple count", (long)it, (long)nt);
+            for (uint32_t r = 0; r < nt; ++r) {
+                const uint32_t wb = I.win + 3 * r;
+                if (wb + 2 >= n)
+                    return fail("triple window out of range", (long)it, (long)wb);
+                const uint32_t q = wq[wb];
+                if (wq[wb + 1] != q || wq[wb + 2] != q || (wb > 0 && wq[wb - 1] == q) ||
+                    (wb + 3 < n && wq[wb + 3] == q))
+                    return fail("triple item window not a whole triple", (long)it, (long)wb);
+                if (wm[wb + 2] != wm[wb] + wm[wb + 1] || wm[wb + 2] > (uint32_t)kLocalSlots)
+                    return fail("triple union", (long)wb, (long)wm[wb + 2]);
+                for (uint32_t e = 0; e < 3; ++e) {
+                    if (local_item[wb + e] >= 0)
+                        return fail("window in two items", (long)(wb + e), (long)it);
+                    local_item[wb + e] = (int)it;
+                }
+                slots += (wm[wb + 2] + 1u) & ~1u;
+                maxm = std::max(maxm, wm[wb + 2]);
+            }
+            if (slots > (uint32_t)kLocalSlots)
+                return fail("triple slots", (long)it, (long)slots);
+            if (nt * plan_pow2(maxm) > (uint32_t)kLocalSort)
+                return fail("triple sort entries", (long)it, (long)(nt * plan_pow2(maxm)));
+        } else if (I.info & kItemLocal) {
             uint32_t nw = I.info & 0xFFu, slots = 0, maxm = 2;
             if (nw < 1 || nw > (uint32_t)kLocalWindows || (I.info & 0x7FFFFF00u))
                 return fail("local window count", (long)it, (long)nw);
@@ -264,10 +296,11 @@ int main(int argc, char **argv)
             }
         }
         for (int plain = 0; plain < 2; ++plain)
-            if (check(wm, wq, count, plain != 0)) {
-                std::printf("case %d style %d plain %d\n", c, style, plain);
-                return 1;
-            }
+            for (int fuse = 0; fuse < 2; ++fuse)
+                if (check(wm, wq, count, plain != 0, fuse != 0)) {
+                    std::printf("case %d style %d plain %d fuse %d\n", c, style, plain, fuse);
+                    return 1;
+                }
     }
     for (int c = 0; c < cases; ++c) {
         std::vector<PartDesc> pd(1 + rng() % 40);
