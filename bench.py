@@ -11,9 +11,9 @@ and 1.037e12 ordered point pairs, k = 4, Eq. (2) estimator.  Series are
 resident in HBM before timing starts.
 
 A step = one pass over the whole workload: its consecutive batches (each at
-most 2^18 queries) replayed back to back on one stream, each run = descriptor
-upload, clear, persistent main kernel (neighbours, counts, digamma sums,
-estimates, noise flags), result download.  `value` = windows / (wall time per
+most 2^18 queries) replayed back to back, alternating between two streams,
+each run = descriptor upload, clear, persistent main kernel (neighbours,
+counts, digamma sums, estimates, noise flags), result download.  `value` = windows / (wall time per
 step).  The roofline object is for the dominant kernel, main_kernel<4>:
 achieved = 8 VALU ops x the distances its neighbour searches compute (per
 launch, counted by wmi_batch_count_evals: m (m - 1) per brute-forced window,
@@ -156,16 +156,19 @@ def headline(args, wmi, torch, w) -> dict:
     for r in first:
         assert np.all(np.isfinite(r["mi_base"])) and np.all(np.isfinite(r["mi_union"]))
     log(f"headline: {len(batches)} batches, first submit {t_submit:.2f} s")
+    # consecutive batches alternate between two streams, so that one batch's
+    # descriptor upload and result download overlap its neighbour's kernel
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     for _ in range(max(1, args.warmup)):
-        for b in batches:
-            b.replay(direct=True)
+        for i, b in enumerate(batches):
+            b.replay(stream=streams[i % 2], direct=True)
     for b in batches:
         b.wait()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        for b in batches:
-            b.replay(direct=True)
+        for i, b in enumerate(batches):
+            b.replay(stream=streams[i % 2], direct=True)
     for b in batches:
         b.wait()
     torch.cuda.synchronize()
@@ -271,6 +274,46 @@ def multiscale(args, wmi, torch, synth) -> dict:
                                 "samples": int(len(lat)), "what": "fresh submit of the whole batch to results on host"},
            "plain_gpu": plain}
     log(f"multiscale: {out}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the plain workload: a stride-1 sweep, incremental against window by window
+# ---------------------------------------------------------------------------
+
+def plain_sweep(args, wmi, torch, synth) -> dict:
+    """One pair of 4096 points, w = 128, stride 1 (3,969 windows): the
+    incremental form (each window from the one before, Section 7.1.2) and
+    every window on its own, each timed over pipelined direct runs."""
+    w = synth.config1()
+    out = {"workload": w.name, "windows": len(w.queries), "ordered_pairs": w.ordered_pairs}
+    with wmi.Store(0) as st:
+        ids = [st.add_series(s) for s in w.series]
+        q = w.queries.copy()
+        q["a"], q["b"] = ids
+        res = {}
+        for name, kw in (("incremental", {}), ("window_by_window", {"no_reuse": True})):
+            b = st.submit(q, k=w.k, **kw)
+            res[name] = b.read()
+            for _ in range(30):
+                b.replay(direct=True)
+            b.wait()
+            torch.cuda.synchronize()
+            steps = max(args.steps, 50)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                b.replay(direct=True)
+            b.wait()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            tim = b.timing()
+            ev = b.count_evals()
+            b.destroy()
+            out[name] = {"ms_per_step": ms, "windows_per_s": len(q) / (ms / 1e3), "main_kernel_ms": tim["main_ms"],
+                         "distances": int(ev)}
+        assert np.array_equal(res["incremental"].view(np.uint8), res["window_by_window"].view(np.uint8))
+    out["kernel_speedup"] = out["window_by_window"]["main_kernel_ms"] / out["incremental"]["main_kernel_ms"]
+    log(f"plain sweep: {out}")
     return out
 
 
@@ -555,6 +598,7 @@ def main():
         del src, dst
     if not args.no_multiscale:
         out["multiscale"] = multiscale(args, wmi, torch, synth)
+        out["plain_sweep"] = plain_sweep(args, wmi, torch, synth)
     if not args.no_serve:
         out["serving"] = serve_bench(args, torch, synth, wmi)
     if not args.no_large:

@@ -390,7 +390,9 @@ typedef struct {
     uint64_t windows_visited;    /* windows the sequential rule examined          */
     uint64_t windows_evaluated;  /* windows evaluated on the device (a noise
                                     triple counts 3)                              */
-    uint64_t ordered_pairs;      /* sum of m (m - 1) over evaluated windows       */
+    uint64_t ordered_pairs;      /* distances computed: m (m - 1) per window; a
+                                    noise triple of at most 512 points counts its
+                                    union's only (parts come from its scan)       */
     uint64_t noise_detections;   /* shifted windows whose new part was noise      */
     uint64_t noise_skips;        /* shifts cancelled after p detections in a row  */
     uint64_t batches;            /* batches submitted                             */

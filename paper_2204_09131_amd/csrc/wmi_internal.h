@@ -45,6 +45,17 @@ constexpr uint32_t kItemLocal = 0x80000000u;
 constexpr uint32_t kItemPrep = 0x40000000u;  // sort a split window's marginals
 constexpr uint32_t kItemTriple = 0x20000000u;  // noise triples evaluated through their unions
 constexpr int kTripleMax = 5;                   // triples per triple item
+// Sweep items: runs of equally spaced windows of one series pair, each window
+// derived from the one before (points removed and added).  A run qualifies
+// when kSweepMinM <= m, m + stride <= kSweepRing and kSweepStrideDiv * stride
+// <= m; kSweepWindows windows per item.  Up to kSweepShared searches and
+// recounts a step are shared by whole waves.
+constexpr uint32_t kItemSweep = 0x10000000u;
+constexpr int kSweepRing = 256;  // one ring slot per thread
+constexpr int kSweepMinM = 2 * kMaxK + 2;
+constexpr int kSweepStrideDiv = 16;
+constexpr int kSweepWindows = 8;
+constexpr int kSweepShared = 64;
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
 // Device scratch of the allocation-free entry point: one static array per
 // device (descriptors, sorted data, counters, estimates of one call).

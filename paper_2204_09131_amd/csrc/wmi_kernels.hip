@@ -17,6 +17,9 @@
 //               each point's base or extension list and its union list
 //               come from one scan over the union, so a triple costs the
 //               distances of its union only.
+//   sweep item  up to 8 equally spaced windows of one pair (stride at most
+//               m / 16): the first in full, each next one from the one
+//               before by removing and adding points (influenced regions).
 //   local item  up to 16 consecutive windows of at most 512 points in total
 //               (whole queries where they fit).
 //               One workgroup stages them in LDS, finds every point's
@@ -1989,6 +1992,465 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
 }
 
 // --------------------------------------------------------------------------
+// sweep items: a run of equally spaced windows, updated point by point
+// --------------------------------------------------------------------------
+// Windows [c s, c s + m) (c = 0 .. C-1, indices relative to the run's first
+// point) of one series pair share m - s points with their neighbour.  The
+// first window is evaluated in full; each later one is derived from the one
+// before by removing its first s points and adding the next s, with the
+// influenced regions of Section 7.1.2 (Definitions 7.1-7.2, Lemmas 1-4):
+//   - a point whose list holds a removed point (the removed point lay in its
+//     influenced region) searches the new window again;
+//   - any other point keeps its list and inserts the added points' keys,
+//     which enter exactly when they lie in its influenced region;
+//   - added points search the whole window;
+//   - a point whose radii did not change updates its marginal counts by the
+//     removed and added points inside its influenced marginal regions; the
+//     others, and the added points, count again.
+// The searches and recounts of a step's few points are shared by whole
+// waves (64 lanes over the window's candidates, then a butterfly merge or a
+// sum).  Keys are (d << ib) | j with j the run-relative index (the same
+// order as the window-relative index) and 2^ib >= the run's span.  The
+// points sit in a ring of R = pow2(m + s) <= kSweepRing slots in LDS; slot r
+// is owned by thread r mod 256, which keeps that point's list, radii and
+// counts in registers.  Results equal those of a full scan of every window.
+
+struct SweepShared {
+    int32_t mn[2], mx[2];
+    uint32_t nwork, nrec;
+    uint32_t offc;       // off-grid points of the current window
+    unsigned long long acc;
+};
+
+// The k smallest keys of one query point among window candidates [lo, lo +
+// n), the point itself (index self) excluded, by the whole wave: lane l takes
+// candidates lo + l, lo + l + 64, ...; after the butterfly every lane holds
+// the merged list.  Returns the candidates evaluated.
+template <int K>
+__device__ __forceinline__ void sweep_wave_search(const uint32_t *__restrict__ ring, uint32_t rmask, int lo, int n,
+                                                  int self, uint32_t qx, uint32_t qy, uint32_t (&t)[K])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        t[r] = 0xFFFFFFFFu;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        const int j = lo + j0 + lane;
+        const uint32_t s = (uint32_t)min(j, lo + n - 1) & rmask;
+        const uint32_t cx = ring[2 * s], cy = ring[2 * s + 1];
+        uint32_t key = tmax(sad_key_v(qx, cx, (uint32_t)j), sad_key_v(qy, cy, (uint32_t)j));
+        key = (j0 + lane < n && j != self) ? key : 0xFFFFFFFFu;
+        insert_sorted<K>(t, key);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t other[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            other[r] = (uint32_t)__shfl_xor((int)t[r], o, 64);
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            insert_sorted<K>(t, other[r]);
+    }
+}
+
+// Marginal counts of one query point over window candidates [lo, lo + n),
+// the point itself excluded, by the whole wave (every lane gets the sums):
+// |d| <= e (estimator 0) or |d| < e (estimator 1), in key units.
+__device__ __forceinline__ void sweep_wave_count(const uint32_t *__restrict__ ring, uint32_t rmask, int lo, int n,
+                                                 int self, uint32_t qx, uint32_t qy, uint32_t ex, uint32_t ey,
+                                                 uint32_t est, int &cx, int &cy)
+{
+    const int lane = threadIdx.x & 63;
+    int nx = 0, ny = 0;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        const int j = lo + j0 + lane;
+        if (j0 + lane < n && j != self) {
+            const uint32_t s = (uint32_t)j & rmask;
+            const uint32_t dx = sad_u32(qx, ring[2 * s], 0u), dy = sad_u32(qy, ring[2 * s + 1], 0u);
+            nx += est == 0 ? (dx <= ex) : (dx < ex);
+            ny += est == 0 ? (dy <= ey) : (dy < ey);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        nx += __shfl_xor(nx, o, 64);
+        ny += __shfl_xor(ny, o, 64);
+    }
+    cx = nx;
+    cy = ny;
+}
+
+// Radii of a point from its k-list (key units): estimator 0 the largest
+// |dx|, |dy| over its neighbours (their coordinates from the ring), 1 the
+// joint k-th distance in both.
+template <int K>
+__device__ __forceinline__ void sweep_radii(const uint32_t (&t)[K], const uint32_t *ring, uint32_t rmask, uint32_t ib,
+                                            uint32_t qx, uint32_t qy, uint32_t est, uint32_t &ex, uint32_t &ey)
+{
+    if (est == 0) {
+        uint32_t rx = 0, ry = 0;
+        const uint32_t imask = (1u << ib) - 1u;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const uint32_t s = (t[r] & imask) & rmask;
+            rx = tmax(rx, sad_u32(qx, ring[2 * s], 0u));
+            ry = tmax(ry, sad_u32(qy, ring[2 * s + 1], 0u));
+        }
+        ex = rx;
+        ey = ry;
+    } else {
+        ex = ey = (t[K - 1] >> ib) << ib;
+    }
+}
+
+__device__ __forceinline__ int sweep_pred(uint32_t d, uint32_t e, uint32_t est)
+{
+    return est == 0 ? (d <= e ? 1 : 0) : (d < e ? 1 : 0);
+}
+
+// Returns false, having evaluated nothing, when the run's value range does not
+// fit 32-bit keys (the caller then evaluates its windows as local items).
+template <int K>
+__device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint32_t *buf, SweepShared &W)
+{
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const WinDesc d0 = a.win[w0];
+    const int m = (int)d0.m;
+    const int s = (int)(a.win[w0 + 1].x - d0.x);  // the plan gives C >= 2 windows at a constant stride
+    const int N = (int)(nwin - 1u) * s + m;        // the run's points
+    const float *X = d0.x, *Y = d0.y;
+
+    // ---- the run's extrema and key width
+    if (tid == 0) {
+        W.mn[0] = W.mn[1] = INT32_MAX;
+        W.mx[0] = W.mx[1] = INT32_MIN;
+        W.acc = 0ull;
+        W.offc = 0u;
+    }
+    block_sync();
+    {
+        int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
+        uint32_t off = 0;  // off-grid values are flagged per window below
+        for (int i = tid; i < N; i += kBlock) {
+            const int32_t xi = grid_int(X[i], off), yi = grid_int(Y[i], off);
+            mnx = min(mnx, xi);
+            mxx = max(mxx, xi);
+            mny = min(mny, yi);
+            mxy = max(mxy, yi);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mnx = min(mnx, __shfl_xor(mnx, o, 64));
+            mxx = max(mxx, __shfl_xor(mxx, o, 64));
+            mny = min(mny, __shfl_xor(mny, o, 64));
+            mxy = max(mxy, __shfl_xor(mxy, o, 64));
+        }
+        if ((tid & 63) == 0) {
+            atomicMin(&W.mn[0], mnx);
+            atomicMax(&W.mx[0], mxx);
+            atomicMin(&W.mn[1], mny);
+            atomicMax(&W.mx[1], mxy);
+        }
+    }
+    block_sync();
+    const int32_t mnx = W.mn[0], mny = W.mn[1];
+    const uint32_t ib = ceil_log2((uint32_t)N);
+    const uint32_t range = (uint32_t)(W.mx[0] - mnx) | (uint32_t)(W.mx[1] - mny);
+    if ((range >> (32 - ib)) != 0u)
+        return false;  // 32-bit keys do not fit
+    const uint32_t est = a.estimator;
+    const int R = (int)(1u << ceil_log2((uint32_t)(m + s)));
+    const uint32_t rmask = (uint32_t)R - 1u;
+    uint32_t *ring = buf;                                      // 2 words per slot, R <= kSweepRing
+    uint32_t *lists = buf + 2 * kSweepRing;                    // kSweepShared x K: lists of searched points
+    uint32_t *work = lists + kSweepShared * kMaxK;             // kSweepShared slots to search
+    uint32_t *rec = work + kSweepShared;                       // kSweepShared slots to recount
+    uint32_t *recr = rec + kSweepShared;                       // their radii (2 each)
+    int32_t *recn = reinterpret_cast<int32_t *>(recr + 2 * kSweepShared);  // their counts (2 each)
+
+    // per owned slot (slot tid and tid + 256): the point's state
+    constexpr int Q = kSweepRing / kBlock;
+    uint32_t Lk[Q][K], QX[Q], QY[Q], EX[Q], EY[Q];
+    int NX[Q], NY[Q], WI[Q];
+    bool OFF[Q];
+    auto stage = [&](int j, int q) {
+        uint32_t o = 0;
+        const int32_t xi = grid_int(X[j], o), yi = grid_int(Y[j], o);
+        QX[q] = (uint32_t)(xi - mnx) << ib;
+        QY[q] = (uint32_t)(yi - mny) << ib;
+        ring[2 * (j & (int)rmask)] = QX[q];
+        ring[2 * (j & (int)rmask) + 1] = QY[q];
+        OFF[q] = o != 0u;
+    };
+
+    // ---- the first window, in full
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int r = tid + kBlock * q;
+        OFF[q] = false;
+        if (r < m)
+            stage(r, q);
+    }
+    block_sync();
+    long long term = 0;
+    uint32_t offn = 0;
+    {
+        // each owner scans the window for its slots (k+1 keys, itself dropped)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = tid + kBlock * q;
+            const bool live = r < m;
+            const uint32_t qx = live ? QX[q] : 0u, qy = live ? QY[q] : 0u;
+            uint32_t t[K + 1];
+#pragma unroll
+            for (int e = 0; e <= K; ++e)
+                t[e] = 0xFFFFFFFFu;
+            if (__ballot(live) != 0ull) {
+                for (int j = 0; j < m; ++j) {
+                    const uint32_t key = tmax(sad_key(qx, ring[2 * j], (uint32_t)j), sad_key(qy, ring[2 * j + 1], (uint32_t)j));
+                    insert_sorted<K + 1>(t, key);
+                }
+                count_evals_lanes(a, live ? (uint32_t)(m - 1) : 0u);
+            }
+            // drop the point's own key (index r, distance 0)
+#pragma unroll
+            for (int e = 0; e < K; ++e)
+                Lk[q][e] = t[e] < (uint32_t)r ? t[e] : t[e + 1];
+            if (live) {
+                sweep_radii<K>(Lk[q], ring, rmask, ib, qx, qy, est, EX[q], EY[q]);
+                int cx = 0, cy = 0;
+                for (int j = 0; j < m; ++j) {
+                    if (j == r)
+                        continue;
+                    cx += sweep_pred(sad_u32(qx, ring[2 * j], 0u), EX[q], est);
+                    cy += sweep_pred(sad_u32(qy, ring[2 * j + 1], 0u), EY[q], est);
+                }
+                NX[q] = cx;
+                NY[q] = cy;
+                if (est != 0 && EX[q] == 0u)
+                    NX[q] = NY[q] = 0;
+                term += est == 0 ? a.psi_fix[NX[q]] + a.psi_fix[NY[q]] : a.psi_fix[NX[q] + 1] + a.psi_fix[NY[q] + 1];
+                offn += OFF[q] ? 1u : 0u;
+            }
+        }
+    }
+
+    for (int c = 0;; ++c) {
+        // ---- window c is complete: its estimate and result
+        for (int o = 32; o > 0; o >>= 1) {
+            term += __shfl_xor(term, o, 64);
+            offn += (uint32_t)__shfl_xor((int)offn, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&W.acc, (unsigned long long)term);
+            if (offn)
+                atomicAdd(&W.offc, offn);
+        }
+        block_sync();
+        if (tid == 0) {
+            const uint32_t w = w0 + (uint32_t)c;
+            const double mi = window_estimate<K>(a, m, (long long)W.acc);
+            const uint32_t fl = W.offc ? kFlagOffGrid : 0u;
+            a.wmi[w] = mi;
+            a.wflags[w] = fl;
+            const uint32_t qi = a.win[w].query;
+            store_result(a, qi, compose_result(a.qd[qi], &mi, &fl));
+            W.acc = 0ull;
+            W.offc = 0u;
+            W.nwork = 0u;
+            W.nrec = 0u;
+        }
+        if (c + 1 >= (int)nwin)
+            break;
+        term = 0;
+        offn = 0;
+
+        // ---- step to window c + 1: points [lo, nlo) leave, [lo + m, lo + m + s) enter
+        const int lo = c * s, nlo = lo + s;
+        int cat[Q];  // 0 empty, 1 leaving, 2 remaining, 3 entering
+        int J[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = tid + kBlock * q;
+            const int j = lo + ((r - lo) & (int)rmask);
+            J[q] = j;
+            cat[q] = r >= R ? 0 : (j < nlo ? 1 : (j < lo + m ? 2 : (j < lo + m + s ? 3 : 0)));
+            if (cat[q] == 3)
+                stage(j, q);
+        }
+        block_sync();  // entering points staged; counters cleared
+        // a point keeps its list unless it holds a leaving point; the others
+        // insert the entering points' keys
+        uint32_t ins = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            WI[q] = -1;
+            bool search = cat[q] == 3;
+            if (cat[q] == 2) {
+                const uint32_t imask = (1u << ib) - 1u;
+                bool stale = false;
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    stale = stale || (int)(Lk[q][e] & imask) < nlo;
+                if (stale) {
+                    search = true;
+                } else {
+                    for (int j = lo + m; j < lo + m + s; ++j) {
+                        const uint32_t sl = (uint32_t)j & rmask;
+                        const uint32_t key =
+                            tmax(sad_key_v(QX[q], ring[2 * sl], (uint32_t)j), sad_key_v(QY[q], ring[2 * sl + 1], (uint32_t)j));
+                        insert_sorted<K>(Lk[q], key);
+                    }
+                    ins += (uint32_t)s;
+                }
+            }
+            if (search) {
+                const uint32_t wi = atomicAdd(&W.nwork, 1u);
+                WI[q] = (int)wi;
+                if (wi < (uint32_t)kSweepShared)
+                    work[wi] = (uint32_t)(tid + kBlock * q);
+            }
+        }
+        count_evals_lanes(a, ins);
+        block_sync();
+        const uint32_t nwork = W.nwork;
+        if (nwork <= (uint32_t)kSweepShared) {
+            for (uint32_t wi = (uint32_t)wave; wi < nwork; wi += kBlock / 64) {
+                const uint32_t r = work[wi];
+                const int j = nlo + (int)((r - (uint32_t)nlo) & rmask);
+                uint32_t t[K];
+                sweep_wave_search<K>(ring, rmask, nlo, m, j, ring[2 * r], ring[2 * r + 1], t);
+                if ((tid & 63) == 0) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        lists[wi * K + e] = t[e];
+                }
+            }
+            count_evals(a, (int)((nwork + (kBlock / 64) - 1 - (uint32_t)wave) / (kBlock / 64)), m - 1);
+            block_sync();
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (WI[q] >= 0) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        Lk[q][e] = lists[WI[q] * K + e];
+                }
+        } else {
+            // many searches at once (ties on the removed points): each owner alone
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool need = WI[q] >= 0;
+                if (__ballot(need) == 0ull)
+                    continue;
+                uint32_t t[K];
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    t[e] = 0xFFFFFFFFu;
+                for (int j = nlo; j < nlo + m; ++j) {
+                    const uint32_t sl = (uint32_t)j & rmask;
+                    uint32_t key =
+                        tmax(sad_key_v(QX[q], ring[2 * sl], (uint32_t)j), sad_key_v(QY[q], ring[2 * sl + 1], (uint32_t)j));
+                    key = j == J[q] ? 0xFFFFFFFFu : key;
+                    insert_sorted<K>(t, key);
+                }
+                count_evals_lanes(a, need ? (uint32_t)(m - 1) : 0u);
+                if (need) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        Lk[q][e] = t[e];
+                }
+            }
+        }
+        // ---- radii and counts of the new window
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            WI[q] = -1;
+            if (cat[q] != 2 && cat[q] != 3)
+                continue;
+            uint32_t ex, ey;
+            sweep_radii<K>(Lk[q], ring, rmask, ib, QX[q], QY[q], est, ex, ey);
+            if (cat[q] == 2 && ex == EX[q] && ey == EY[q]) {
+                // Lemmas 3-4: the same radii, counts move by the leaving and
+                // entering points inside the marginal regions
+                int dxn = 0, dyn = 0;
+                for (int j = lo; j < nlo; ++j) {
+                    const uint32_t sl = (uint32_t)j & rmask;
+                    dxn -= sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), ex, est);
+                    dyn -= sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), ey, est);
+                }
+                for (int j = lo + m; j < lo + m + s; ++j) {
+                    const uint32_t sl = (uint32_t)j & rmask;
+                    dxn += sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), ex, est);
+                    dyn += sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), ey, est);
+                }
+                NX[q] += dxn;
+                NY[q] += dyn;
+            } else {
+                EX[q] = ex;
+                EY[q] = ey;
+                const uint32_t ri = atomicAdd(&W.nrec, 1u);
+                WI[q] = (int)ri;
+                if (ri < (uint32_t)kSweepShared) {
+                    rec[ri] = (uint32_t)(tid + kBlock * q);
+                    recr[2 * ri] = ex;
+                    recr[2 * ri + 1] = ey;
+                }
+            }
+        }
+        block_sync();
+        const uint32_t nrec = W.nrec;
+        if (nrec <= (uint32_t)kSweepShared) {
+            for (uint32_t ri = (uint32_t)wave; ri < nrec; ri += kBlock / 64) {
+                const uint32_t r = rec[ri];
+                const int j = nlo + (int)((r - (uint32_t)nlo) & rmask);
+                int cx, cy;
+                sweep_wave_count(ring, rmask, nlo, m, j, ring[2 * r], ring[2 * r + 1], recr[2 * ri], recr[2 * ri + 1],
+                                 est, cx, cy);
+                if ((tid & 63) == 0) {
+                    recn[2 * ri] = cx;
+                    recn[2 * ri + 1] = cy;
+                }
+            }
+            block_sync();
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (WI[q] >= 0) {
+                    NX[q] = recn[2 * WI[q]];
+                    NY[q] = recn[2 * WI[q] + 1];
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool need = WI[q] >= 0;
+                if (__ballot(need) == 0ull)
+                    continue;
+                int cx = 0, cy = 0;
+                for (int j = nlo; j < nlo + m; ++j) {
+                    const uint32_t sl = (uint32_t)j & rmask;
+                    if (j != J[q]) {
+                        cx += sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), EX[q], est);
+                        cy += sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), EY[q], est);
+                    }
+                }
+                if (need) {
+                    NX[q] = cx;
+                    NY[q] = cy;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (cat[q] != 2 && cat[q] != 3)
+                continue;
+            int nx = NX[q], ny = NY[q];
+            if (est != 0 && EX[q] == 0u)
+                nx = ny = 0;
+            term += est == 0 ? a.psi_fix[nx] + a.psi_fix[ny] : a.psi_fix[nx + 1] + a.psi_fix[ny + 1];
+            offn += OFF[q] ? 1u : 0u;
+        }
+    }
+    return true;
+}
+
+// --------------------------------------------------------------------------
 // main: persistent loop over items
 // --------------------------------------------------------------------------
 template <int K>
@@ -1997,6 +2459,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
     __shared__ TripleShared T;
+    __shared__ SweepShared SW;
     __shared__ long long s_part[kBlock / 64];
     __shared__ int32_t s_red[5];
     __shared__ uint32_t s_cnt[64];
@@ -2020,7 +2483,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
         if (it >= a.n_items)
             break;
         const Item itm = a.item[a.item_begin + it];
-        if (itm.info & kItemTriple) {
+        if (itm.info & kItemSweep) {
+            if (!sweep_item<K>(a, itm.win, itm.info & 0xFFu, buf, SW)) {
+                // values too widely spread for 32-bit keys: every window on its own
+                for (uint32_t c = 0; c < (itm.info & 0xFFu); ++c) {
+                    block_sync();
+                    local_item<K>(a, itm.win + c, 1u, buf, L);
+                }
+            }
+        } else if (itm.info & kItemTriple) {
             triple_item<K>(a, itm.win, itm.info & 0xFFu, buf, T);
         } else if (itm.info & kItemLocal) {
             local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);

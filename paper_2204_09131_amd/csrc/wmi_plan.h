@@ -44,9 +44,16 @@ inline uint32_t plan_pow2(uint32_t v)
 // union has at most kLocalSlots points go to triple items: consecutive
 // triples, up to kTripleMax of them, kLocalSlots union points (each padded
 // to even) and kLocalSort sort entries (triples x the power of two at or
-// above the largest union).
+// above the largest union).  With wx, wy (the address of each window's
+// first x and y value) runs of one-window queries of the same m whose
+// windows advance by a constant stride s in both series (kSweepMinM <= m,
+// m + s <= kSweepRing, kSweepStrideDiv s <= m) go to sweep items of
+// kSweepWindows windows (the last one or two items of a run share its
+// remainder, never leaving one window alone).  Reuse (triple and sweep items)
+// is off with fuse_triples false.
 inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wquery, uint64_t count,
-                       bool plain, Plan &out, bool fuse_triples = true)
+                       bool plain, Plan &out, bool fuse_triples = true, const std::vector<uint64_t> *wx = nullptr,
+                       const std::vector<uint64_t> *wy = nullptr)
 {
     const uint64_t n_win = wm.size();
     out = Plan();
@@ -93,12 +100,44 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         }
         tri = Cur();
     };
+    // the window is its query's only one
+    auto single = [&](uint64_t v) {
+        return (v == 0 || wquery[v - 1] != wquery[v]) && (v + 1 >= n_win || wquery[v + 1] != wquery[v]);
+    };
+    const bool sweeps = !plain && fuse_triples && wx && wy && wx->size() == n_win && wy->size() == n_win;
     uint32_t w = 0;
     for (uint64_t t = 0; t < count; ++t) {
         const uint32_t w0 = w;
         uint32_t nw = 0;
         while (w0 + nw < n_win && wquery[w0 + nw] == (uint32_t)t)
             ++nw;
+        if (sweeps && nw == 1 && w0 + 1 < n_win && single(w0 + 1) && wm[w0 + 1] == wm[w0]) {
+            // a run of equally spaced one-window queries
+            const uint32_t m = wm[w0];
+            const int64_t dx = (int64_t)((*wx)[w0 + 1] - (*wx)[w0]), dy = (int64_t)((*wy)[w0 + 1] - (*wy)[w0]);
+            const int64_t s = dx / (int64_t)sizeof(float);
+            if (dx == dy && dx > 0 && dx % (int64_t)sizeof(float) == 0 && m >= (uint32_t)kSweepMinM &&
+                (int64_t)m + s <= kSweepRing && kSweepStrideDiv * s <= (int64_t)m) {
+                uint64_t e = w0 + 1;
+                while (e + 1 < n_win && single(e + 1) && wm[e + 1] == m && (*wx)[e + 1] - (*wx)[e] == (uint64_t)dx &&
+                       (*wy)[e + 1] - (*wy)[e] == (uint64_t)dy)
+                    ++e;
+                close();
+                close_tri();
+                uint64_t rest = e + 1 - w0;
+                while (rest > 0) {
+                    const uint64_t c = rest <= (uint64_t)kSweepWindows
+                                           ? rest
+                                           : (rest == (uint64_t)kSweepWindows + 1 ? rest / 2 : (uint64_t)kSweepWindows);
+                    out.items.push_back(Item{w, kItemSweep | (uint32_t)c});
+                    out.cost.push_back((uint64_t)m * m + c * (uint64_t)m * (uint64_t)(16 + 2 * s));
+                    w += (uint32_t)c;
+                    rest -= c;
+                }
+                t = wquery[w - 1];  // the loop moves on to the query after the run
+                continue;
+            }
+        }
         if (!plain && fuse_triples && nw == 3 && wm[w0 + 2] <= (uint32_t)kLocalSlots) {
             close();  // a local item holds consecutive windows only
             const uint32_t mu = wm[w0 + 2];
@@ -196,7 +235,7 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
         std::vector<uint32_t> cnt(66, 0);
         std::vector<size_t> idx;
         for (size_t i = 0; i < P.items.size(); ++i) {
-            const bool local = (P.items[i].info & (kItemLocal | kItemTriple)) != 0;
+            const bool local = (P.items[i].info & (kItemLocal | kItemTriple | kItemSweep)) != 0;
             const int ph = local ? (P.cost[i] < kTailCost ? 2 : 0) : 1;
             if (ph == phase) {
                 cnt[bucket(P.cost[i]) + 1]++;

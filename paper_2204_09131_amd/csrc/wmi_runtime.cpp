@@ -81,6 +81,7 @@ constexpr int kSlots = 16;  // runs whose timings are kept
 
 struct wmi_batch {
     wmi_store *st = nullptr;
+    size_t dev_cap = 0, host_cap = 0;  // allocated sizes of dev and host
     uint64_t count = 0;
     hipStream_t stream = nullptr;
     wmi_params params{};
@@ -112,6 +113,56 @@ struct wmi_batch {
 };
 
 namespace {
+
+constexpr size_t kSpareBytes = size_t(256) << 20;  // parked buffers kept per kind
+constexpr size_t kSpareCount = 8;
+
+// A parked buffer of at least `bytes` (the smallest that fits, if it is not
+// more than four times too large), else a new allocation.
+hipError_t take_buffer(wmi_store *st, bool device, size_t bytes, char **out, size_t *cap)
+{
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto &v = device ? st->spare_dev : st->spare_host;
+        size_t best = v.size();
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i].bytes >= bytes && v[i].bytes <= 4 * bytes + 4096 && (best == v.size() || v[i].bytes < v[best].bytes))
+                best = i;
+        if (best < v.size()) {
+            *out = v[best].p;
+            *cap = v[best].bytes;
+            (device ? st->spare_dev_bytes : st->spare_host_bytes) -= v[best].bytes;
+            v.erase(v.begin() + (long)best);
+            return hipSuccess;
+        }
+    }
+    *cap = bytes;
+    void *p = nullptr;
+    hipError_t e = device ? hipMalloc(&p, bytes) : hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    *out = static_cast<char *>(p);
+    return e;
+}
+
+// Keep a buffer for reuse while the parked total stays small, else free it.
+void park_buffer(wmi_store *st, bool device, char *p, size_t cap)
+{
+    if (!p)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto &v = device ? st->spare_dev : st->spare_host;
+        size_t &tot = device ? st->spare_dev_bytes : st->spare_host_bytes;
+        if (v.size() < kSpareCount && tot + cap <= kSpareBytes) {
+            v.push_back(wmi_store::Spare{p, cap});
+            tot += cap;
+            return;
+        }
+    }
+    if (device)
+        (void)hipFree(p);
+    else
+        (void)hipHostFree(p);
+}
 
 bool value_on_grid(float v)
 {
@@ -393,6 +444,10 @@ int wmi_store_destroy(wmi_store *st)
     for (Series &s : st->series)
         if (s.live && s.owned)
             (void)hipFree((void *)s.d);
+    for (const wmi_store::Spare &sp : st->spare_dev)
+        (void)hipFree(sp.p);
+    for (const wmi_store::Spare &sp : st->spare_host)
+        (void)hipHostFree(sp.p);
     (void)hipFree(st->psi_d);
     (void)hipFree(st->psi_fix);
     (void)hipStreamDestroy(st->stream);
@@ -581,6 +636,7 @@ struct BatchBuild {
     std::vector<Series> ser;
     std::vector<uint64_t> wstart;  // windows in query order (a triple: base, extension, union)
     std::vector<uint32_t> wm, wquery, used;
+    std::vector<uint64_t> wx, wy;  // address of each window's first x and y value
     uint64_t pairs = 0, n_win = 0, n_items = 0, n_prep = 0;
     bool plain = false;
     Plan plan;
@@ -606,6 +662,8 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
             return rc;
         for (uint32_t r = 0; r < nw; ++r) {
             B.wstart.push_back(s3[r]);
+            B.wx.push_back((uint64_t)(uintptr_t)(B.ser[qs[t].a].d + s3[r]));
+            B.wy.push_back((uint64_t)(uintptr_t)(B.ser[qs[t].b].d + s3[r]));
             B.wm.push_back(m3[r]);
             B.wquery.push_back((uint32_t)t);
             B.pairs += (uint64_t)m3[r] * (m3[r] - 1);
@@ -622,7 +680,7 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
 
     // ---- work items ---------------------------------------------------------
     B.plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
-    plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE));
+    plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE), &B.wx, &B.wy);
     if (!B.plain)
         plan_queue(B.plan, B.wm, B.queue);
     B.n_items = B.plain ? B.plan.items.size() : B.queue.size();
@@ -786,11 +844,11 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         delete b;
         return rc;
     };
-    hipError_t e = hipMalloc(&b->dev, dev_bytes);
+    hipError_t e = take_buffer(st, true, dev_bytes, &b->dev, &b->dev_cap);
     if (e != hipSuccess)
         return bail(e, "hipMalloc(batch)");
     b->host_bytes = desc_bytes + align_up(B.res_bytes, 256);
-    e = hipHostMalloc(&b->host, std::max<size_t>(b->host_bytes, 256), hipHostMallocDefault);
+    e = take_buffer(st, false, std::max<size_t>(b->host_bytes, 256), &b->host, &b->host_cap);
     if (e != hipSuccess)
         return bail(e, "hipHostMalloc(batch)");
     e = hipEventCreate(&b->ev_end);
@@ -1087,10 +1145,8 @@ int wmi_batch_destroy(wmi_batch *b)
                 (void)hipEventDestroy(e);
     if (b->ev_end)
         (void)hipEventDestroy(b->ev_end);
-    if (b->dev)
-        (void)hipFree(b->dev);
-    if (b->host)
-        (void)hipHostFree(b->host);
+    park_buffer(st, true, b->dev, b->dev_cap);
+    park_buffer(st, false, b->host, b->host_cap);
     delete b;
     return WMI_OK;
 }

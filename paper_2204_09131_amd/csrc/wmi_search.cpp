@@ -28,6 +28,16 @@ namespace {
 constexpr uint64_t kChunkQueries = 1ull << 18;
 constexpr uint64_t kChunkPoints = 1ull << 26;
 
+// Distances the path computes for a window of m points, or for a noise triple
+// (base m, extension e): a triple whose union fits a triple item costs its
+// union's only (its parts' lists come from the union's scan).
+uint64_t window_pairs(uint64_t m) { return m * (m - 1); }
+uint64_t triple_pairs(uint64_t m, uint64_t e)
+{
+    const uint64_t u = m + e;
+    return u <= (uint64_t)kLocalSlots ? window_pairs(u) : window_pairs(m) + window_pairs(e) + window_pairs(u);
+}
+
 struct Eval {
     double mi = 0.0;   // I(w)
     bool noise = false;
@@ -69,9 +79,8 @@ int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> 
             out[i0 + i].noise = (r[i].flags & WMI_F_NOISE) != 0;
         }
         stats.batches++;
-        const uint64_t m = s_w, mo = s_w - delta, md = delta;
         stats.windows_evaluated += triple ? 3 * n : n;
-        stats.ordered_pairs += n * (triple ? m * (m - 1) + mo * (mo - 1) + md * (md - 1) : m * (m - 1));
+        stats.ordered_pairs += n * (triple ? triple_pairs(s_w - delta, delta) : window_pairs(s_w));
     }
     return WMI_OK;
 }
@@ -283,10 +292,10 @@ int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params
             const uint64_t m = q[i].len, e = q[i].ext_len;
             if (q[i].ext_side) {
                 stats.windows_evaluated += 3;
-                stats.ordered_pairs += m * (m - 1) + e * (e - 1) + (m + e) * (m + e - 1);
+                stats.ordered_pairs += triple_pairs(m, e);
             } else {
                 stats.windows_evaluated += 1;
-                stats.ordered_pairs += m * (m - 1);
+                stats.ordered_pairs += window_pairs(m);
             }
         }
         i0 = i1;

@@ -79,6 +79,15 @@ struct wmi_store {
     std::string poison_msg;
     std::set<wmi_batch *> batches;
     std::set<wmi_server *> servers;
+    // buffers of destroyed batches kept for the next submits (a driver that
+    // submits thousands of small batches would otherwise allocate and free
+    // device and pinned memory every time)
+    struct Spare {
+        char *p;
+        size_t bytes;
+    };
+    std::vector<Spare> spare_dev, spare_host;
+    size_t spare_dev_bytes = 0, spare_host_bytes = 0;
 };
 
 namespace wmi {

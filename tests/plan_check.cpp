@@ -19,10 +19,10 @@ static int fail(const char *what, long a, long b)
 }
 
 static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wq, uint64_t count, bool plain,
-                 bool fuse)
+                 bool fuse, const std::vector<uint64_t> &wx, const std::vector<uint64_t> &wy)
 {
     Plan P;
-    plan_items(wm, wq, count, plain, P, fuse);
+    plan_items(wm, wq, count, plain, P, fuse, &wx, &wy);
     const size_t n = wm.size();
     if (P.items.size() != P.cost.size())
         return fail("cost size", (long)P.items.size(), (long)P.cost.size());
@@ -30,7 +30,33 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
     std::vector<std::vector<uint32_t>> split_q0(n);
     for (size_t it = 0; it < P.items.size(); ++it) {
         const Item &I = P.items[it];
-        if (I.info & kItemTriple) {
+        auto single = [&](size_t v) {
+            return (v == 0 || wq[v - 1] != wq[v]) && (v + 1 >= n || wq[v + 1] != wq[v]);
+        };
+        if (I.info & kItemSweep) {
+            // equally spaced one-window queries of one m, within the ring
+            const uint32_t nw = I.info & 0xFFu;
+            if (plain || !fuse)
+                return fail("sweep item without reuse", (long)it, (long)nw);
+            if (nw < 2 || nw > (uint32_t)kSweepWindows || (I.info & 0x0FFFFF00u) || I.win + nw > n)
+                return fail("sweep window count", (long)it, (long)nw);
+            const uint32_t m = wm[I.win];
+            const int64_t dx = (int64_t)(wx[I.win + 1] - wx[I.win]), dy = (int64_t)(wy[I.win + 1] - wy[I.win]);
+            const int64_t s = dx / 4;
+            if (dx != dy || dx <= 0 || dx % 4 || m < (uint32_t)kSweepMinM || (int64_t)m + s > kSweepRing ||
+                kSweepStrideDiv * s > (int64_t)m)
+                return fail("sweep shape", (long)it, (long)s);
+            for (uint32_t r = 0; r < nw; ++r) {
+                const uint32_t v = I.win + r;
+                if (!single(v) || wm[v] != m)
+                    return fail("sweep window", (long)it, (long)v);
+                if (r && (wx[v] - wx[v - 1] != (uint64_t)dx || wy[v] - wy[v - 1] != (uint64_t)dy))
+                    return fail("sweep stride", (long)it, (long)v);
+                if (local_item[v] >= 0)
+                    return fail("window in two items", (long)v, (long)it);
+                local_item[v] = (int)it;
+            }
+        } else if (I.info & kItemTriple) {
             // whole noise triples (base, extension, union of one query), the
             // union within the limits of the kernel's LDS layout
             const uint32_t nt = I.info & 0xFFu;
@@ -270,8 +296,9 @@ int main(int argc, char **argv)
     std::mt19937_64 rng(12345);
     for (int c = 0; c < cases; ++c) {
         std::vector<uint32_t> wm, wq;
+        std::vector<uint64_t> wx, wy;
         uint64_t count = 1 + rng() % 400;
-        int style = (int)(rng() % 4);
+        int style = (int)(rng() % 5);
         for (uint64_t t = 0; t < count; ++t) {
             auto draw = [&]() -> uint32_t {
                 switch (style) {
@@ -281,23 +308,38 @@ int main(int argc, char **argv)
                 default: return (uint32_t)(1 + rng() % 64);
                 }
             };
-            if (rng() % 3 == 0) {  // a noise triple: base, extension, union
+            if (style == 4 && rng() % 2 == 0) {  // a run of equally spaced windows
+                const uint32_t m = (uint32_t)(kSweepMinM - 2 + rng() % 480), s = 1 + (uint32_t)(rng() % (m / 12 + 1));
+                const uint64_t L = 1 + rng() % 30, bx = (rng() % 1000000) * 4, by = (rng() % 1000000) * 4;
+                for (uint64_t i = 0; i < L && t < count; ++i, ++t) {
+                    wm.push_back(m);
+                    wq.push_back((uint32_t)t);
+                    wx.push_back(bx + 4 * i * s);
+                    wy.push_back(by + 4 * i * s);
+                }
+                --t;
+            } else if (rng() % 3 == 0) {  // a noise triple: base, extension, union
                 uint32_t base = draw(), ext = 1 + (uint32_t)(rng() % 300);
                 if (base + ext > 4096)
                     base = 4096 - ext;
                 wm.push_back(base);
                 wm.push_back(ext);
                 wm.push_back(base + ext);
-                for (int r = 0; r < 3; ++r)
+                for (int r = 0; r < 3; ++r) {
                     wq.push_back((uint32_t)t);
+                    wx.push_back(rng() & ~3ull);
+                    wy.push_back(rng() & ~3ull);
+                }
             } else {
                 wm.push_back(draw());
                 wq.push_back((uint32_t)t);
+                wx.push_back(rng() & ~3ull);
+                wy.push_back(rng() & ~3ull);
             }
         }
         for (int plain = 0; plain < 2; ++plain)
             for (int fuse = 0; fuse < 2; ++fuse)
-                if (check(wm, wq, count, plain != 0, fuse != 0)) {
+                if (check(wm, wq, count, plain != 0, fuse != 0, wx, wy)) {
                     std::printf("case %d style %d plain %d fuse %d\n", c, style, plain, fuse);
                     return 1;
                 }

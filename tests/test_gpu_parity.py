@@ -283,10 +283,15 @@ def test_count_evals(store, cfg1, orc):
     skipped, fewer for split windows whose x order lets the scan stop; the
     counting run rewrites the same results."""
     w, q = cfg1
-    b = store.submit(q, k=4)
+    b = store.submit(q, k=4, no_reuse=True)
     first = b.read().copy()
     m = q["len"].astype(np.int64)
     assert b.count_evals() == int(np.sum(m * (m - 1)))  # one window length: local items scan m - 1 each
+    assert b.read().tobytes() == first.tobytes()
+    b.destroy()
+    # the stride-1 sweep with reuse (each window from the one before) computes fewer
+    b = store.submit(q, k=4)
+    assert b.count_evals() < int(np.sum(m * (m - 1))) // 3
     assert b.read().tobytes() == first.tobytes()
     b.destroy()
     # constant x: every |dx| is 0, no side of an outward scan can close
