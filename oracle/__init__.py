@@ -67,6 +67,8 @@ class Oracle:
         lib.oracle_window_mi.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
         lib.oracle_batch.restype = ctypes.c_int
+        lib.oracle_window_entropy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_window_entropy.restype = ctypes.c_double
         lib.oracle_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_void_p]
@@ -109,6 +111,13 @@ class Oracle:
         y = np.ascontiguousarray(y, dtype=np.float32)
         return self.lib.oracle_window_mi(x.ctypes.data, y.ctypes.data, x.shape[0], k, estimator)
 
+    def window_entropy(self, x, y) -> float:
+        """Empirical entropy of the window's pairs (Section 5.4), natural log."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        assert x.shape == y.shape
+        return self.lib.oracle_window_entropy(x.ctypes.data, y.ctypes.data, x.shape[0])
+
     # -- batches ----------------------------------------------------------
     def batch(self, series, queries, k: int = 4, estimator: int = 0, tau: float = 0.0,
               tau_normalize: int = 0, threads: int = 0) -> np.ndarray:
@@ -125,7 +134,7 @@ class Oracle:
         rc = self.lib.oracle_batch(ptrs, q.ctypes.data, len(q), k, estimator, float(tau),
                                    int(tau_normalize), out.ctypes.data)
         if rc != 0:
-            raise ValueError("k out of range")
+            raise ValueError("k or tau_normalize out of range")
         return out
 
     def threads(self, n: int = 0) -> int:

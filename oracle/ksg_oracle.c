@@ -210,6 +210,42 @@ double oracle_window_mi(const float *x, const float *y, int m, int k, int estima
 }
 
 /* ---------------------------------------------------------------------- */
+/* window entropy for the normalised MI of Section 5.4                     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * H_w of Eq. (normalizedMI)'s denominator, read as the entropy of the
+ * window's empirical distribution (the printed formula lacks its minus sign
+ * and names p^(x_i, y_i), the relative frequency of a sample pair):
+ *     H_w = - sum over the distinct pairs v of p_v ln p_v,  p_v = c_v / m,
+ * with c_v the number of points of the window equal to v in both
+ * coordinates.  Written out directly: each distinct pair is taken at its
+ * first occurrence, its multiplicity counted over the whole window.
+ * Natural logarithm; 0 for m = 1; ln m when every pair is distinct.
+ */
+double oracle_window_entropy(const float *x, const float *y, int m)
+{
+    if (m < 1)
+        return NAN;
+    double h = 0.0;
+    for (int i = 0; i < m; ++i) {
+        int first = 1;
+        for (int j = 0; j < i && first; ++j)
+            if (x[j] == x[i] && y[j] == y[i])
+                first = 0;
+        if (!first)
+            continue;
+        int c = 0;
+        for (int j = 0; j < m; ++j)
+            if (x[j] == x[i] && y[j] == y[i])
+                ++c;
+        const double p = (double)c / (double)m;
+        h -= p * log(p);
+    }
+    return h;
+}
+
+/* ---------------------------------------------------------------------- */
 /* batches of queries over a set of series                                 */
 /* ---------------------------------------------------------------------- */
 
@@ -255,14 +291,16 @@ static double window_of(const float *const *series, const oracle_query *q, uint6
  * as applied in Section 6.2): base w_o = [start, start+len), extension w_d
  * of ext_len samples adjacent on the given side, union w'' = w_o with w_d.
  *   noise  <=>  I(w_o) > 0  and  I(w_d) < tau_eff  and  I(w'') < I(w_o)
- * with tau_eff = tau, or tau * ln(ext_len) when tau_normalize is set.
+ * with tau_eff = tau (tau_normalize 0), tau * ln(ext_len) (1: the window
+ * entropy of Section 5.4 when every pair of w_d is distinct), or tau * H(w_d)
+ * with H the empirical entropy of oracle_window_entropy (2).
  * Series bounds are not checked here; callers pass valid queries.
  * Queries are independent; they are spread over threads with OpenMP.
  */
 int oracle_batch(const float *const *series, const oracle_query *qs, int64_t count, int k,
                  int estimator, double tau, int tau_normalize, oracle_result *out)
 {
-    if (k < 1 || k > ORACLE_K_MAX)
+    if (k < 1 || k > ORACLE_K_MAX || tau_normalize < 0 || tau_normalize > 2)
         return -1;
     if (!psi_ready)
         build_psi();
@@ -282,7 +320,12 @@ int oracle_batch(const float *const *series, const oracle_query *qs, int64_t cou
             r.mi_ext = window_of(series, q, ext_start, q->ext_len, k, estimator, &f);
             r.mi_union = window_of(series, q, uni_start, q->len + q->ext_len, k, estimator, &f);
             if (!(f & FLAG_TOO_SHORT)) {
-                double tau_eff = tau_normalize ? tau * log((double)q->ext_len) : tau;
+                double tau_eff = tau;
+                if (tau_normalize == 1)
+                    tau_eff = tau * log((double)q->ext_len);
+                else if (tau_normalize == 2)
+                    tau_eff = tau * oracle_window_entropy(series[q->a] + ext_start, series[q->b] + ext_start,
+                                                          (int)q->ext_len);
                 if (!(r.mi_base > 0.0))
                     f |= FLAG_NONPOS_BASE;
                 else if (r.mi_ext < tau_eff && r.mi_union < r.mi_base)

@@ -19,16 +19,27 @@ Readings (the library's driver takes the same ones):
 * the uncorrelated partitions handed to lower layers are the stretches of a
   partition not covered by its correlated windows, kept if at least s_min
   long;
-* with ``normalize`` the thresholds scale with the entropy ln m of m distinct
-  samples: I_w >= sigma ln|w| and I(w_d) < tau ln|w_d|.
+* with ``normalize`` the thresholds scale with the window entropy of the
+  normalised MI (Section 5.4): normalize=1 takes ln m, the entropy of m
+  distinct samples (I_w >= sigma ln|w|, I(w_d) < tau ln|w_d|); normalize=2
+  takes ``entropy(start, length)``, any function giving H of the window
+  (tests pass the oracle's empirical entropy of the window's pairs).
 """
 from __future__ import annotations
 
 import math
 
 
+def _scale(normalize, entropy, start: int, length: int) -> float:
+    """The factor sigma and tau are multiplied by for the window [start,
+    start + length): 1, ln length, or its entropy."""
+    if normalize == 2:
+        return entropy(start, length)
+    return math.log(length) if normalize else 1.0
+
+
 def top_down(mi, begin: int, end: int, s_max: int, s_min: int, sigma: float, tau: float = 0.0,
-             p: int = 0, step_div: int = 8, normalize: bool = False, trace: list | None = None):
+             p: int = 0, step_div: int = 8, normalize: int = 0, trace: list | None = None, entropy=None):
     """Correlated windows as (start, length, layer, I) in ascending start
     order.  ``trace`` (a list) receives every window the rule examines, as
     (layer, start)."""
@@ -37,8 +48,6 @@ def top_down(mi, begin: int, end: int, s_max: int, s_min: int, sigma: float, tau
     s_w, layer = s_max, 0
     while s_w >= s_min and partitions:
         delta = max(1, s_w // step_div)
-        corr_thr = sigma * math.log(s_w) if normalize else sigma
-        noise_thr = tau * math.log(delta) if normalize else tau
         pruning = p > 0 and delta < s_w
         lower = []
         for ps, pe in partitions:
@@ -50,7 +59,7 @@ def top_down(mi, begin: int, end: int, s_max: int, s_min: int, sigma: float, tau
                 if trace is not None:
                     trace.append((layer, t))
                 I = mi(t, s_w)
-                if I >= corr_thr:                      # correlated: report, move past it
+                if I >= sigma * _scale(normalize, entropy, t, s_w):   # correlated: report, move past it
                     found.append((t, s_w, layer, I))
                     if t - uncovered >= s_min:
                         lower.append((uncovered, t))
@@ -63,7 +72,7 @@ def top_down(mi, begin: int, end: int, s_max: int, s_min: int, sigma: float, tau
                 if pruning and came_by_shift:          # Definition 6.2 on (overlap, new part)
                     I_o = mi(t, s_w - delta)
                     I_d = mi(t + s_w - delta, delta)
-                    noise = I_o > 0 and I_d < noise_thr and I < I_o
+                    noise = I_o > 0 and I_d < tau * _scale(normalize, entropy, t + s_w - delta, delta) and I < I_o
                 detections = detections + 1 if noise else 0
                 if pruning and detections >= p:        # p detections in a row: no more shifting
                     t += s_w
@@ -94,8 +103,8 @@ def splitmix64(z: int) -> int:
 
 
 def bottom_up(mi, begin: int, end: int, s_min: int, s_max: int, delta: int, sigma: float,
-              max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: bool = False,
-              chunk: int = 0, seed: int = 0, trace: list | None = None):
+              max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: int = 0,
+              chunk: int = 0, seed: int = 0, trace: list | None = None, entropy=None):
     """Algorithm 2 (Section 5.2) with the directional pruning of Section 6.3,
     chunk by chunk, one climb after another.  Readings (the library's driver
     takes the same ones):
@@ -112,7 +121,9 @@ def bottom_up(mi, begin: int, end: int, s_min: int, s_max: int, delta: int, sigm
     * pruning: the ring's pure left and pure right extensions are noise
       triples over w; a direction closes for the rest of the climb after p
       consecutive examined extensions of it were noise (Definition 6.2);
-    * a window is reported when I >= sigma (normalize: sigma ln|w|).
+    * a window is reported when I >= sigma (normalize 1: sigma ln|w|;
+      2: sigma H(w)); a noise test compares with tau, tau ln|w_d| or
+      tau H(w_d) likewise.
     ``trace`` receives every examined window as (start, end)."""
     found = []
     size = chunk if chunk else max(end - begin, 1)
@@ -148,11 +159,11 @@ def bottom_up(mi, begin: int, end: int, s_min: int, s_max: int, delta: int, sigm
                         I = mi(s, e - s)
                         if p and de == 0 and ds == -r:      # w extended on the left
                             ext = ws - s
-                            thr = tau * math.log(ext) if normalize else tau
+                            thr = tau * _scale(normalize, entropy, s, ext)
                             seen["left"] = Iw > 0 and mi(s, ext) < thr and I < Iw
                         if p and ds == 0 and de == r:       # w extended on the right
                             ext = e - we
-                            thr = tau * math.log(ext) if normalize else tau
+                            thr = tau * _scale(normalize, entropy, we, ext)
                             seen["right"] = Iw > 0 and mi(we, ext) < thr and I < Iw
                         if not math.isnan(I) and (best is None or I > best[2]):
                             best = (s, e, I)
@@ -170,7 +181,7 @@ def bottom_up(mi, begin: int, end: int, s_min: int, s_max: int, delta: int, sigm
                 for side in ("left", "right"):
                     if p and runs[side] >= p:
                         closed[side] = True
-            thr_w = sigma * math.log(we - ws) if normalize else sigma
+            thr_w = sigma * _scale(normalize, entropy, ws, we - ws)
             if Iw >= thr_w:
                 found.append((ws, we - ws, 0, Iw))
             rest = we

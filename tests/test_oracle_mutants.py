@@ -44,13 +44,25 @@ MUTANTS = {
     "noise_ext_compare": ("r.mi_ext < tau_eff && r.mi_union < r.mi_base", "r.mi_ext < tau_eff && r.mi_union > r.mi_base"),
     "noise_ext_side_swapped": ("q->start + q->len : q->start - q->ext_len", "q->start - q->ext_len : q->start + q->len"),
     # the normalised threshold tau * ln|w_d| of the new part
-    "tau_norm_log2": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
-                      "tau_normalize ? tau * log2((double)q->ext_len) : tau"),
-    "tau_norm_union": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
-                       "tau_normalize ? tau * log((double)(q->len + q->ext_len)) : tau"),
-    "tau_norm_base": ("tau_normalize ? tau * log((double)q->ext_len) : tau",
-                      "tau_normalize ? tau * log((double)q->len) : tau"),
-    "tau_norm_ignored": ("tau_normalize ? tau * log((double)q->ext_len) : tau", "tau"),
+    "tau_norm_log2": ("tau_eff = tau * log((double)q->ext_len);", "tau_eff = tau * log2((double)q->ext_len);"),
+    "tau_norm_union": ("tau_eff = tau * log((double)q->ext_len);",
+                       "tau_eff = tau * log((double)(q->len + q->ext_len));"),
+    "tau_norm_base": ("tau_eff = tau * log((double)q->ext_len);", "tau_eff = tau * log((double)q->len);"),
+    "tau_norm_ignored": ("tau_eff = tau * log((double)q->ext_len);", "tau_eff = tau;"),
+    # the window entropy of Section 5.4 and the threshold tau * H(w_d)
+    "entropy_sign": ("h -= p * log(p);", "h += p * log(p);"),
+    "entropy_log2": ("h -= p * log(p);", "h -= p * log2(p);"),
+    "entropy_x_only": ("""            if (x[j] == x[i] && y[j] == y[i])
+                ++c;""", """            if (x[j] == x[i])
+                ++c;"""),
+    "entropy_every_point": ("""        if (!first)
+            continue;""", ""),
+    "entropy_over_m_minus_1": ("(double)c / (double)m;", "(double)c / (double)(m - 1);"),
+    "tau_entropy_of_base": ("oracle_window_entropy(series[q->a] + ext_start, series[q->b] + ext_start,\n"
+                            "                                                          (int)q->ext_len)",
+                            "oracle_window_entropy(series[q->a] + q->start, series[q->b] + q->start,\n"
+                            "                                                          (int)q->len)"),
+    "tau_entropy_as_ln": ("tau_eff = tau * oracle_window_entropy(", "tau_eff = tau * 0.0 + tau * log((double)q->ext_len) + 0.0 * oracle_window_entropy("),
 }
 
 
@@ -111,6 +123,22 @@ def pin_suite(orc):
     q = synth.make_queries(0, 1, 0, 16, 8, +1)
     for tau, noise in ((0.22, False), (0.30, True)):
         res = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=1)[0]
+        assert bool(res["flags"] & oracle.FLAG_NOISE) == noise
+    # window entropy: closed forms, counts, and the threshold tau * H(w_d)
+    m = 7
+    v = (np.arange(m) / 4096.0).astype(np.float32)
+    assert abs(orc.window_entropy(v, v[::-1].copy()) - math.log(m)) < 1e-12
+    xg = np.array([0, 0, 0, 1], dtype=np.float32)
+    yg = np.array([0, 1, 1, 0], dtype=np.float32)
+    assert abs(orc.window_entropy(xg, yg) - 1.5 * math.log(2)) < 1e-12
+    from scipy.stats import entropy
+    counts = np.array([3, 9, 1, 5])
+    xc = np.repeat(np.arange(4), counts).astype(np.float32)
+    assert abs(orc.window_entropy(xc, xc) - entropy(counts)) < 1e-12
+    from test_oracle_pins import _x_shape_tied_triple
+    x, y = _x_shape_tied_triple()
+    for tau, noise in ((0.0055, False), (0.0080, True)):
+        res = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=2)[0]
         assert bool(res["flags"] & oracle.FLAG_NOISE) == noise
 
 

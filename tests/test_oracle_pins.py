@@ -414,3 +414,105 @@ def test_noise_flag_normalized_threshold(orc, tau, noise):
     # without normalisation the raw threshold decides: never noise here
     r = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=0)[0]
     assert not r["flags"] & oracle.FLAG_NOISE
+
+
+# --------------------------------------------------------------------------
+# window entropy H_w (Section 5.4, the denominator of the normalised MI),
+# read as the entropy of the window's empirical distribution of pairs
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m", [1, 2, 7, 256, 4096])
+def test_entropy_all_distinct_is_ln_m(orc, m):
+    x = (np.arange(m) / 4096.0).astype(np.float32)
+    y = np.random.default_rng(m).permutation(x)
+    assert orc.window_entropy(x, y) == pytest.approx(math.log(m), abs=1e-12)
+
+
+@pytest.mark.parametrize("m", [1, 5, 300])
+def test_entropy_constant_window_is_zero(orc, m):
+    v = np.full(m, 0.75, dtype=np.float32)
+    assert orc.window_entropy(v, -v) == 0.0
+
+
+def test_entropy_two_equal_clusters_is_ln2(orc):
+    x = np.array([0.5] * 6 + [0.25] * 6, dtype=np.float32)
+    y = np.array([1.0] * 6 + [2.0] * 6, dtype=np.float32)
+    assert orc.window_entropy(x, y) == pytest.approx(math.log(2), abs=1e-15)
+
+
+def test_entropy_pairs_not_coordinates(orc):
+    """Pairs that agree in one coordinate only are distinct: the grid
+    {0,1} x {0,1}, each cell twice, has entropy ln 4 (ln 2 per coordinate)."""
+    x = np.array([0, 0, 1, 1, 0, 0, 1, 1], dtype=np.float32)
+    y = np.array([0, 1, 0, 1, 1, 0, 1, 0], dtype=np.float32)
+    assert orc.window_entropy(x, y) == pytest.approx(math.log(4), abs=1e-15)
+    assert orc.window_entropy(x, np.zeros(8, np.float32)) == pytest.approx(math.log(2), abs=1e-15)
+    # unequal multiplicities: (0,0) once, (0,1) twice, (1,0) once
+    x = np.array([0, 0, 0, 1], dtype=np.float32)
+    y = np.array([0, 1, 1, 0], dtype=np.float32)
+    assert orc.window_entropy(x, y) == pytest.approx(1.5 * math.log(2), abs=1e-15)
+
+
+def test_entropy_signed_zero_is_one_value(orc):
+    x = np.array([0.0, -0.0, 0.0, -0.0], dtype=np.float32)
+    assert orc.window_entropy(x, x) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_entropy_against_scipy(orc, seed):
+    """Multiplicities drawn at random; scipy's entropy of the count vector
+    is the same quantity."""
+    from scipy.stats import entropy
+    r = np.random.default_rng(seed)
+    counts = r.integers(1, 40, size=r.integers(1, 30))
+    vals = r.permutation(np.arange(len(counts)))
+    x = np.repeat(vals, counts).astype(np.float32) / 8.0
+    y = np.repeat(vals % 3, counts).astype(np.float32)
+    perm = r.permutation(len(x))
+    assert orc.window_entropy(x[perm], y[perm]) == pytest.approx(entropy(counts), abs=1e-12)
+
+
+def _x_shape_tied_triple():
+    """The X-shaped triple with a tie-heavy extension: 16-point ramp, then 4
+    anti-diagonal points each taken twice, so H(w_d) = ln 4 against ln 8."""
+    u = 1.0 / 4096.0
+    j = np.repeat(np.arange(4), 2)
+    x = np.concatenate([np.arange(16) * u, 4 * j * u]).astype(np.float32)
+    y = np.concatenate([np.arange(16) * u, (15 - 4 * j) * u]).astype(np.float32)
+    return x, y
+
+
+# tau, expected noise bit under tau * H(w_d) (the empirical entropy, ln 4
+# here); tau * ln|w_d| = tau ln 8 decides the first case the other way.
+@pytest.mark.parametrize("tau,noise", [(0.0055, False), (0.0080, True)])
+def test_noise_flag_entropy_threshold(orc, tau, noise):
+    import oracle
+    x, y = _x_shape_tied_triple()
+    i_o = brute_mi(x[:16], y[:16], 4, 0)
+    i_d = brute_mi(x[16:], y[16:], 4, 0)
+    i_u = brute_mi(x, y, 4, 0)
+    assert i_o > 0 and i_u < i_o and i_d > 0
+    assert (i_d < tau * math.log(4)) == noise
+    assert abs(i_d - tau * math.log(4)) > 0.001
+    q = synth.make_queries(0, 1, 0, 16, 8, +1)
+    r = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=2)[0]
+    assert r["mi_ext"] == pytest.approx(i_d, abs=1e-12)
+    assert bool(r["flags"] & oracle.FLAG_NOISE) == noise
+    r1 = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=1)[0]
+    assert bool(r1["flags"] & oracle.FLAG_NOISE) == (i_d < tau * math.log(8))
+    if not noise:
+        assert r1["flags"] & oracle.FLAG_NOISE  # the two readings part here
+
+
+def test_entropy_threshold_equals_log_threshold_when_distinct(orc):
+    """Tie-free extensions: the entropy reading reduces to tau * ln|w_d|."""
+    x, y = synth.cfg2_pair(4096, 7)
+    starts = np.arange(0, 3000, 37, dtype=np.uint64)
+    q = synth.make_queries(0, 1, starts, 256, 64, +1)
+    for tau in (0.01, 0.05, 0.2):
+        a = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=1)
+        b = orc.batch([x, y], q, k=4, tau=tau, tau_normalize=2)
+        for s in starts:
+            e0 = int(s) + 256
+            assert len(set(zip(x[e0:e0 + 64].tolist(), y[e0:e0 + 64].tolist()))) == 64
+        assert np.array_equal(a["flags"], b["flags"])

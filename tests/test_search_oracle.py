@@ -187,7 +187,53 @@ PRUNED_LEFT_TRACE = [(0, 32), (0, 48), (16, 48), (0, 32), (0, 48), (0, 64), (16,
                      (48, 80), (48, 96), (64, 96)]
 
 
+def td_entropy_noise_case(srch):
+    """normalize=2: the thresholds take the window entropy H(start, length)
+    given by the caller.  The 64-point layer of the first case with the new
+    part scoring 0.15 and H = ln|w| except for the window starting at 64,
+    whose entropy is halved (ties): tau H = 0.104 there, so the first shift
+    (new part [64, 72)) is not noise and the second ([72, 80)) is."""
+    vals = {64: 0.3, 56: 0.4, 8: 0.15}
+    ent = lambda s, m: math.log(m) * (0.5 if s == 64 else 1.0)  # noqa: E731
+    trace = []
+    srch.top_down(lambda t, m: vals[m], 0, 200, 64, 64, 10.0, tau=0.1, p=1, normalize=2, trace=trace, entropy=ent)
+    return [t for _, t in trace]
+
+
+def bu_entropy_cases(srch):
+    """normalize=2 with every window's entropy half of ln|w|: the left
+    extensions' new parts (0.2) stay above tau H = 0.139, so the left side
+    stays open; the climb of I = |w| / 1000 to 128 points (0.128) is reported
+    for sigma = 0.05 (sigma H = 0.121) and not for 0.054 (0.131)."""
+    ent = lambda s, m: 0.5 * math.log(m)  # noqa: E731
+    trace = []
+    srch.bottom_up(lambda s, m: s / 1000.0 if m >= 32 else 0.2, 0, 96, 32, 64, 16, 0.01, max_idle=0, history=1,
+                   tau=0.1, p=1, normalize=2, trace=trace, entropy=ent)
+    rep = [[(s, m) for s, m, _, _ in srch.bottom_up(lambda s, m: m / 1000.0, 0, 300, 64, 128, 16, sg, max_idle=1,
+                                                     history=1, normalize=2, entropy=ent)] for sg in (0.05, 0.054)]
+    return trace, rep
+
+
+def td_report_case(srch, normalize):
+    """64-point windows score 0.3, new parts 0.25 (never noise), sigma 0.1:
+    0.3 < sigma ln 64 = 0.416, so nothing is correlated with normalize=1,
+    though the raw sigma would report every window; with normalize=2 and the
+    window at 0 of entropy ln 64 / 2 (sigma H = 0.208) that one is."""
+    vals = {64: 0.3, 56: 0.4, 8: 0.25}
+    ent = lambda s, m: math.log(m) * (0.5 if s == 0 else 1.0)  # noqa: E731
+    trace = []
+    srch.top_down(lambda t, m: vals[m], 0, 200, 64, 64, 0.1, tau=0.1, p=1, normalize=normalize, trace=trace,
+                  entropy=ent)
+    return [t for _, t in trace]
+
+
 def normalized_pin_suite(srch):
+    assert td_report_case(srch, 1) == list(range(0, 137, 8))
+    assert td_report_case(srch, 2) == [0] + list(range(64, 137, 8))
+    assert td_entropy_noise_case(srch) == [0, 8, 16, 80, 88]
+    trace, rep = bu_entropy_cases(srch)
+    assert trace[8:11] == [(16, 48), (16, 64), (16, 80)]
+    assert rep == [[(0, 128), (128, 128)], []]
     assert td_normalized_noise_case(srch, 0.15) == [0, 8, 72, 80]
     assert td_normalized_noise_case(srch, 0.25) == list(range(0, 137, 8))
     found, trace = bu_normalized_noise_case(srch, 0.2)
@@ -203,17 +249,21 @@ def test_normalized_noise_and_report_thresholds():
 
 
 SEARCH_MUTANTS = {
-    "td_noise_log2": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log2(delta)"),
-    "td_noise_window": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log(s_w)"),
-    "td_noise_overlap": ("noise_thr = tau * math.log(delta)", "noise_thr = tau * math.log(s_w - delta)"),
-    "td_noise_raw": ("noise_thr = tau * math.log(delta) if normalize else tau", "noise_thr = tau"),
-    "bu_noise_log2": ("thr = tau * math.log(ext) if normalize else tau",
-                      "thr = tau * math.log2(ext) if normalize else tau"),
-    "bu_noise_union": ("thr = tau * math.log(ext) if normalize else tau",
-                       "thr = tau * math.log(e - s) if normalize else tau"),
-    "bu_noise_raw": ("thr = tau * math.log(ext) if normalize else tau", "thr = tau"),
-    "bu_report_log2": ("thr_w = sigma * math.log(we - ws)", "thr_w = sigma * math.log2(we - ws)"),
-    "bu_report_raw": ("thr_w = sigma * math.log(we - ws) if normalize else sigma", "thr_w = sigma"),
+    "scale_log2": ("return math.log(length) if normalize else 1.0", "return math.log2(length) if normalize else 1.0"),
+    "scale_entropy_ignored": ("""    if normalize == 2:
+        return entropy(start, length)
+""", ""),
+    "td_corr_raw": ("if I >= sigma * _scale(normalize, entropy, t, s_w):", "if I >= sigma:"),
+    "td_noise_window": ("tau * _scale(normalize, entropy, t + s_w - delta, delta)", "tau * _scale(normalize, entropy, t, s_w)"),
+    "td_noise_overlap": ("tau * _scale(normalize, entropy, t + s_w - delta, delta)",
+                         "tau * _scale(normalize, entropy, t, s_w - delta)"),
+    "td_noise_entropy_start": ("tau * _scale(normalize, entropy, t + s_w - delta, delta)",
+                               "tau * _scale(normalize, entropy, t, delta)"),
+    "td_noise_raw": ("I_d < tau * _scale(normalize, entropy, t + s_w - delta, delta)", "I_d < tau"),
+    "bu_noise_union": ("thr = tau * _scale(normalize, entropy, s, ext)", "thr = tau * _scale(normalize, entropy, s, e - s)"),
+    "bu_noise_base": ("thr = tau * _scale(normalize, entropy, s, ext)", "thr = tau * _scale(normalize, entropy, ws, we - ws)"),
+    "bu_noise_raw": ("thr = tau * _scale(normalize, entropy, s, ext)", "thr = tau"),
+    "bu_report_raw": ("thr_w = sigma * _scale(normalize, entropy, ws, we - ws)", "thr_w = sigma"),
 }
 
 
