@@ -146,7 +146,7 @@ def frac(ops, seconds) -> float:
 # ---------------------------------------------------------------------------
 
 def headline(args, wmi, torch, w) -> dict:
-    st = wmi.Store(0, budget_bytes=4 << 30)
+    st = wmi.Store(0, budget_bytes=4 << 30, tuning="auto")
     ids = [st.add_series(s) for s in w.series]
     assert ids == list(range(len(w.series)))
     t0 = time.perf_counter()
@@ -205,7 +205,7 @@ def multiscale(args, wmi, torch, synth) -> dict:
     w = synth.config2()
     n_win = len(w.queries)
     pairs = w.ordered_pairs
-    st = wmi.Store(0)
+    st = wmi.Store(0, tuning="auto")
     ids = [st.add_series(s) for s in w.series]
     q = w.queries.copy()
     q["a"], q["b"] = ids
@@ -287,7 +287,7 @@ def plain_sweep(args, wmi, torch, synth) -> dict:
     every window on its own, each timed over pipelined direct runs."""
     w = synth.config1()
     out = {"workload": w.name, "windows": len(w.queries), "ordered_pairs": w.ordered_pairs}
-    with wmi.Store(0) as st:
+    with wmi.Store(0, tuning="auto") as st:
         ids = [st.add_series(s) for s in w.series]
         q = w.queries.copy()
         q["a"], q["b"] = ids
@@ -336,7 +336,7 @@ def serve_bench(args, torch, synth, wmi) -> dict:
     log(f"serve: generated {n_series} x {n} series in {time.perf_counter() - t_gen:.1f} s")
     t, a, b, w, stride = synth.config4_stream(n_queries=args.serve_queries, n_series=n_series, n=n,
                                               rate=args.serve_rate)
-    st = wmi.Store(0)
+    st = wmi.Store(0, tuning="auto")
     ids = [st.add_series(data[i]) for i in range(n_series)]
     assert ids == list(range(n_series))
     pairs_of = w.astype(np.float64) * (w - 1) * ((n - w) // stride + 1)
@@ -440,7 +440,7 @@ def large_search(args, wmi, torch, synth) -> dict:
     series = synth.config5_series(5, n_series=8)
     n = len(series[0])
     log(f"large search: generated 8 x {n} series in {time.perf_counter() - t_gen:.1f} s")
-    st = wmi.Store(0, budget_bytes=4 << 30)
+    st = wmi.Store(0, budget_bytes=4 << 30, tuning="auto")
     ids = [st.add_series(s) for s in series]
     pairs = [(i, j) for i in range(8) for j in range(i + 1, 8)]
     if args.large_pairs:
@@ -587,6 +587,12 @@ def main():
         "noise_triples": h["noise_triples"],
         "roofline": h["roofline"],
     }
+    # the work-list choices (tile shapes) in use: the autotuner's file for
+    # this architecture when there is one, else the library's defaults
+    with wmi.Store(0, tuning="auto") as st:
+        tf = wmi.tuning_file(0)
+        out["tuning"] = {"source": os.path.relpath(tf, ROOT) if os.path.exists(tf) else "defaults",
+                         **st.get_tuning()}
     if args.copy_calibration:
         # an elementwise kernel of known traffic (reads 256 MiB, writes 256 MiB)
         # that HBM byte counters are scaled by

@@ -66,6 +66,14 @@ extern "C" {
  * extension lists come from its union's scan, so a triple costs its union's
  * distances only).  Results are identical; for comparison. */
 #define WMI_SUBMIT_NO_REUSE 4u
+/* Also compute the entropy H_w of every window of every query (the
+ * denominator of the normalised MI, Section 5.4; read as the entropy of the
+ * window's empirical distribution of pairs, natural log):
+ *     H_w = -sum_v (c_v / m) ln(c_v / m),
+ * c_v the number of the window's m points equal to the pair v in both
+ * coordinates; ln m when all pairs are distinct.  Read with
+ * wmi_read_entropy.  Not accepted by wmi_submit_noalloc. */
+#define WMI_SUBMIT_ENTROPY 8u
 
 typedef struct wmi_store wmi_store;
 typedef struct wmi_batch wmi_batch;
@@ -104,7 +112,14 @@ typedef struct {
  *              1 = Kraskov's first form (joint radius, counts with <,
  *              psi(n_x + 1), no -1/k).
  * tau        : noise threshold of Definition 6.2 (nats).
- * tau_normalize: 0 compare I(w_d) < tau; 1 compare I(w_d) < tau * ln|w_d|.
+ * tau_normalize: how the noise threshold of Definition 6.2 is scaled by the
+ *              extension's entropy (the normalised MI of Section 5.4):
+ *              0 compare I(w_d) < tau;
+ *              1 compare I(w_d) < tau * ln|w_d| (the entropy when every pair
+ *                of w_d is distinct);
+ *              2 compare I(w_d) < tau * H(w_d), H as for WMI_SUBMIT_ENTROPY
+ *                (ties lower it below ln|w_d|); computed on the device by an
+ *                extra pass before the estimates.
  * flags      : WMI_SUBMIT_*.
  */
 typedef struct {
@@ -150,6 +165,40 @@ int wmi_store_create(const wmi_store_desc *desc, wmi_store **out);
 /* Wait for every batch of the store, free its device memory and the store.
  * Batches not yet destroyed become invalid. */
 int wmi_store_destroy(wmi_store *store);
+
+/*
+ * Work-list and scheduling choices of a store (the tile shapes the autotuner
+ * picks per window-size bucket); every choice gives the same results, only
+ * the speed differs.  Buckets and ranges:
+ *   local_windows[b] windows packed into one workgroup's item when the
+ *                    item's largest window has at most 32, 64, 128, 256,
+ *                    512 points (b = 0..4): 1..16 (default 16)
+ *   triples[b]       noise triples per workgroup item, by the largest union
+ *                    in the same buckets: 1..5 (default 5)
+ *   sweep_windows[b] windows of a run of equally spaced windows (stride at
+ *                    most m / 16, m + stride <= 256) that one workgroup
+ *                    derives one from the other (Section 7.1.2), for m <= 64,
+ *                    128, 255: 2..255, or 1: such runs are evaluated window
+ *                    by window (default 8)
+ *   stragglers[b]    for windows above 512 points (m <= 1024, 2048, 4096):
+ *                    a wave stops scanning candidates for its 128 query
+ *                    points together once at most this many can still gain,
+ *                    and finishes those one at a time: 0..128 (default 16)
+ * WMI_EINVAL for a value out of range.  Applies to later submits and newly
+ * created servers of the store.
+ */
+typedef struct {
+    uint32_t local_windows[5];
+    uint32_t triples[5];
+    uint32_t sweep_windows[3];
+    uint32_t stragglers[3];
+} wmi_tuning;
+
+/* Set the store's choices (NULL: the defaults). */
+int wmi_store_set_tuning(wmi_store *store, const wmi_tuning *tuning);
+
+/* The store's current choices. */
+int wmi_store_get_tuning(wmi_store *store, wmi_tuning *out);
 
 /* Copy n float32 values from host memory into a new resident series; the
  * caller keeps ownership of host_values.  NaN/Inf -> WMI_EINVAL; off-grid
@@ -216,6 +265,14 @@ int wmi_done(wmi_batch *batch);
 
 /* Wait for the batch, then copy its `count` results to host_out. */
 int wmi_read(wmi_batch *batch, wmi_result *host_out);
+
+/* Window entropies of a batch submitted with WMI_SUBMIT_ENTROPY: 3 doubles per
+ * query (base, extension, union; a plain window fills the first, NaN in the
+ * others) into host_out (3 * count doubles, caller-owned).  Waits as
+ * wmi_read.  WMI_ESTATE when the batch was submitted without the flag.
+ * H is exact to a few units in the last place: the sum of ln c over the
+ * points is taken in 2^-44 fixed point, independent of the schedule. */
+int wmi_read_entropy(wmi_batch *batch, double *host_out);
 
 /* ---- replay flags ------------------------------------------------------------ */
 #define WMI_REPLAY_DIRECT 1u /* enqueue kernel by kernel (per-kernel timing), no graph */
@@ -414,8 +471,11 @@ typedef struct {
  * one ends.
  *   s_max, s_min : 2 <= s_min <= s_max <= WMI_MAX_WINDOW.
  *   step_div     : 0 means 8.
- *   normalize    : 1 compares I_w >= sigma * ln|w| and I(w_d) < tau * ln|w_d|
- *                  (normalised MI with the entropy of |w| distinct samples).
+ *   normalize    : thresholds of the normalised MI (Section 5.4): 0 compares
+ *                  I_w >= sigma and I(w_d) < tau; 1 compares I_w >= sigma *
+ *                  ln|w| and I(w_d) < tau * ln|w_d| (the entropy of |w|
+ *                  distinct samples); 2 takes the windows' empirical
+ *                  entropies H(w), H(w_d) (WMI_SUBMIT_ENTROPY) instead.
  * Output: the correlated windows in ascending start order (non-overlapping),
  * written to host_out (capacity entries; (end - begin) / s_min + 1 always
  * suffice); *n_out receives their number.  WMI_EINVAL for bad ids, ranges or
@@ -457,8 +517,8 @@ int wmi_td_search(wmi_store *store, uint32_t a, uint32_t b, uint64_t begin, uint
  *     if I(best) > L_h[j] or I(best) > I(w): w = best, idle = 0
  *     else idle += 1;
  *     if I(w) > L_h[j]: L_h[j] = I(w)
- *   report w if I(w) >= sigma (normalize: sigma * ln|w|); the rest starts at
- *   w's end.
+ *   report w if I(w) >= sigma (normalize 1: sigma * ln|w|; 2: sigma * H(w),
+ *   as for wmi_td_search); the rest starts at w's end.
  * Pruning (p > 0): the ring's pure left extension (start - r delta, same end)
  * and pure right extension are evaluated as noise triples over w; when
  * Definition 6.2 flags a direction's extension in p consecutive steps, that

@@ -48,14 +48,50 @@ constexpr int kTripleMax = 5;                   // triples per triple item
 // Sweep items: runs of equally spaced windows of one series pair, each window
 // derived from the one before (points removed and added).  A run qualifies
 // when kSweepMinM <= m, m + stride <= kSweepRing and kSweepStrideDiv * stride
-// <= m; kSweepWindows windows per item.  Up to kSweepShared searches and
-// recounts a step are shared by whole waves.
+// <= m; kSweepWindows windows per item.
 constexpr uint32_t kItemSweep = 0x10000000u;
-constexpr int kSweepRing = 256;  // one ring slot per thread
+constexpr int kSweepRing = 256;  // m + stride: one window point per thread
+constexpr int kSweepSpan = 512;  // points of a sweep item's run, held in LDS
 constexpr int kSweepMinM = 2 * kMaxK + 2;
 constexpr int kSweepStrideDiv = 16;
 constexpr int kSweepWindows = 8;
-constexpr int kSweepShared = 64;
+
+// Work-list and scheduling choices (the tile shapes an autotuner picks per
+// window-size bucket); every choice gives the same results.  Buckets:
+//   local_windows[b]  windows per local item whose largest m is at most
+//                     32, 64, 128, 256, 512 (b = 0..4): 1..kLocalWindows
+//   triples[b]        triples per triple item, by the largest union in the
+//                     same buckets: 1..kTripleMax
+//   sweep_windows[b]  windows per sweep item of m <= 64, 128, 255: 2..255,
+//                     or 1: no sweep items for that bucket
+//   stragglers[b]     open query slots at which a wave of a window scanned in
+//                     x order stops its shared scan (m <= 1024, 2048, 4096):
+//                     0..128
+struct Tuning {
+    uint32_t local_windows[5];
+    uint32_t triples[5];
+    uint32_t sweep_windows[3];
+    uint32_t stragglers[3];
+};
+
+inline Tuning default_tuning()
+{
+    Tuning t;
+    for (int b = 0; b < 5; ++b) {
+        t.local_windows[b] = (uint32_t)kLocalWindows;
+        t.triples[b] = (uint32_t)kTripleMax;
+    }
+    for (int b = 0; b < 3; ++b) {
+        t.sweep_windows[b] = (uint32_t)kSweepWindows;
+        t.stragglers[b] = 16u;
+    }
+    return t;
+}
+
+// (constexpr: usable on the host and the device)
+constexpr int local_bucket(uint32_t m) { return m <= 32 ? 0 : m <= 64 ? 1 : m <= 128 ? 2 : m <= 256 ? 3 : 4; }
+constexpr int sweep_bucket(uint32_t m) { return m <= 64 ? 0 : m <= 128 ? 1 : 2; }
+constexpr int split_bucket(uint32_t m) { return m <= 1024 ? 0 : m <= 2048 ? 1 : 2; }
 constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait gives up
 // Device scratch of the allocation-free entry point: one static array per
 // device (descriptors, sorted data, counters, estimates of one call).
@@ -166,6 +202,20 @@ struct LaunchArgs {
     float *dbg_ex, *dbg_ey;
     // distance evaluations per workgroup (one counter per workgroup), or null
     unsigned long long *evals;
+    uint32_t strag[3];            // straggler thresholds by split_bucket(m)
+};
+
+// Window entropies (the normalised MI of Section 5.4): per query, H of its
+// windows into hres (3 per query, NaN where a query has no such window; null:
+// extensions only), and with set_tau the noise threshold tau * H(extension)
+// into the query's descriptor.
+struct EntropyArgs {
+    const WinDesc *win;
+    QDesc *qd;
+    double *hres;
+    double tau;
+    uint32_t n_query;
+    uint32_t set_tau;
 };
 
 }  // namespace wmi

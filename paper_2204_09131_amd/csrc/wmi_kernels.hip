@@ -964,9 +964,6 @@ __device__ __forceinline__ uint64_t key_below(int64_t v, uint32_t nb)
     return (uint64_t)v << nb;
 }
 
-// A wave stops its shared scan once at most this many of its query slots can
-// still gain from a side; those finish one at a time with the whole wave.
-constexpr int kStragglers = 16;
 
 // One straggler's scan of one side, by the whole wave: candidates from `edge`
 // outwards (RIGHT: edge, edge + 1, ...; left: edge - 1, edge - 2, ...), 256
@@ -1064,7 +1061,9 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
                     any_l = any_l || __ballot(nl[t]) != 0ull;
                 }
                 // a few queries still open: they finish alone below
-                if (needy <= kStragglers)
+                // a few open slots left (the launch's threshold for this
+                // window size): they finish one at a time below
+                if (needy <= (int)a.strag[split_bucket((uint32_t)m)])
                     break;
                 if (any_r) {
                     const int cnt = min(kWaveChunk, m - r);
@@ -2007,77 +2006,20 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
 //   - a point whose radii did not change updates its marginal counts by the
 //     removed and added points inside its influenced marginal regions; the
 //     others, and the added points, count again.
-// The searches and recounts of a step's few points are shared by whole
-// waves (64 lanes over the window's candidates, then a butterfly merge or a
-// sum).  Keys are (d << ib) | j with j the run-relative index (the same
+// The points that search and count again are the step's jobs: a group of 8
+// lanes takes one (each lane an eighth of the window's candidates, then a
+// butterfly merge and a sum), three workgroup barriers a step.  Keys are (d << ib) | j with j the run-relative index (the same
 // order as the window-relative index) and 2^ib >= the run's span.  The
-// points sit in a ring of R = pow2(m + s) <= kSweepRing slots in LDS; slot r
-// is owned by thread r mod 256, which keeps that point's list, radii and
-// counts in registers.  Results equal those of a full scan of every window.
+// run's points (at most kSweepSpan) are read into LDS once; a window point
+// of index j is owned by thread j mod R, R = pow2(m + s) <= 256, which keeps
+// its list, radii and counts in registers.  Results equal those of a full scan of every window.
 
 struct SweepShared {
     int32_t mn[2], mx[2];
-    uint32_t nwork, nrec;
+    uint32_t nwork[2];   // job counters of even and odd windows
     uint32_t offc;       // off-grid points of the current window
     unsigned long long acc;
 };
-
-// The k smallest keys of one query point among window candidates [lo, lo +
-// n), the point itself (index self) excluded, by the whole wave: lane l takes
-// candidates lo + l, lo + l + 64, ...; after the butterfly every lane holds
-// the merged list.  Returns the candidates evaluated.
-template <int K>
-__device__ __forceinline__ void sweep_wave_search(const uint32_t *__restrict__ ring, uint32_t rmask, int lo, int n,
-                                                  int self, uint32_t qx, uint32_t qy, uint32_t (&t)[K])
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int r = 0; r < K; ++r)
-        t[r] = 0xFFFFFFFFu;
-    for (int j0 = 0; j0 < n; j0 += 64) {
-        const int j = lo + j0 + lane;
-        const uint32_t s = (uint32_t)min(j, lo + n - 1) & rmask;
-        const uint32_t cx = ring[2 * s], cy = ring[2 * s + 1];
-        uint32_t key = tmax(sad_key_v(qx, cx, (uint32_t)j), sad_key_v(qy, cy, (uint32_t)j));
-        key = (j0 + lane < n && j != self) ? key : 0xFFFFFFFFu;
-        insert_sorted<K>(t, key);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t other[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            other[r] = (uint32_t)__shfl_xor((int)t[r], o, 64);
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            insert_sorted<K>(t, other[r]);
-    }
-}
-
-// Marginal counts of one query point over window candidates [lo, lo + n),
-// the point itself excluded, by the whole wave (every lane gets the sums):
-// |d| <= e (estimator 0) or |d| < e (estimator 1), in key units.
-__device__ __forceinline__ void sweep_wave_count(const uint32_t *__restrict__ ring, uint32_t rmask, int lo, int n,
-                                                 int self, uint32_t qx, uint32_t qy, uint32_t ex, uint32_t ey,
-                                                 uint32_t est, int &cx, int &cy)
-{
-    const int lane = threadIdx.x & 63;
-    int nx = 0, ny = 0;
-    for (int j0 = 0; j0 < n; j0 += 64) {
-        const int j = lo + j0 + lane;
-        if (j0 + lane < n && j != self) {
-            const uint32_t s = (uint32_t)j & rmask;
-            const uint32_t dx = sad_u32(qx, ring[2 * s], 0u), dy = sad_u32(qy, ring[2 * s + 1], 0u);
-            nx += est == 0 ? (dx <= ex) : (dx < ex);
-            ny += est == 0 ? (dy <= ey) : (dy < ey);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        nx += __shfl_xor(nx, o, 64);
-        ny += __shfl_xor(ny, o, 64);
-    }
-    cx = nx;
-    cy = ny;
-}
 
 // Radii of a point from its k-list (key units): estimator 0 the largest
 // |dx|, |dy| over its neighbours (their coordinates from the ring), 1 the
@@ -2107,12 +2049,68 @@ __device__ __forceinline__ int sweep_pred(uint32_t d, uint32_t e, uint32_t est)
     return est == 0 ? (d <= e ? 1 : 0) : (d < e ? 1 : 0);
 }
 
+constexpr int kSweepGroup = 8;  // lanes sharing one point's search and count
+
+// One point's update by a group of kSweepGroup consecutive lanes: its k
+// nearest among the window's candidates [lo, lo + m) (the point itself,
+// index self, excluded; lane g takes candidates lo + g, lo + g + 8, ...; a
+// three-step butterfly merges the lanes' lists), its radii, then its marginal
+// counts (lanes count their candidates, a butterfly sums).  Every lane of
+// the group ends with the list and the counts.
+template <int K>
+__device__ __forceinline__ void sweep_group_update(const uint32_t *__restrict__ ring, uint32_t rmask, uint32_t ib,
+                                                   int lo, int m, int self, uint32_t est, uint32_t (&t)[K], int &cx,
+                                                   int &cy)
+{
+    const int g = (int)threadIdx.x & (kSweepGroup - 1);
+    const uint32_t sq = (uint32_t)self & rmask;
+    const uint32_t qx = ring[2 * sq], qy = ring[2 * sq + 1];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        t[r] = 0xFFFFFFFFu;
+    for (int i = g; i < m; i += kSweepGroup) {
+        const int j = lo + i;
+        const uint32_t sl = (uint32_t)j & rmask;
+        uint32_t key = tmax(sad_key_v(qx, ring[2 * sl], (uint32_t)j), sad_key_v(qy, ring[2 * sl + 1], (uint32_t)j));
+        key = j == self ? 0xFFFFFFFFu : key;
+        insert_sorted<K>(t, key);
+    }
+#pragma unroll
+    for (int o = kSweepGroup / 2; o > 0; o >>= 1) {
+        uint32_t other[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            other[r] = (uint32_t)__shfl_xor((int)t[r], o, 64);
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            insert_sorted<K>(t, other[r]);
+    }
+    uint32_t ex, ey;
+    sweep_radii<K>(t, ring, rmask, ib, qx, qy, est, ex, ey);
+    int nx = 0, ny = 0;
+    for (int i = g; i < m; i += kSweepGroup) {
+        const int j = lo + i;
+        const uint32_t sl = (uint32_t)j & rmask;
+        if (j != self) {
+            nx += sweep_pred(sad_u32(qx, ring[2 * sl], 0u), ex, est);
+            ny += sweep_pred(sad_u32(qy, ring[2 * sl + 1], 0u), ey, est);
+        }
+    }
+#pragma unroll
+    for (int o = kSweepGroup / 2; o > 0; o >>= 1) {
+        nx += __shfl_xor(nx, o, 64);
+        ny += __shfl_xor(ny, o, 64);
+    }
+    cx = nx;
+    cy = ny;
+}
+
 // Returns false, having evaluated nothing, when the run's value range does not
 // fit 32-bit keys (the caller then evaluates its windows as local items).
 template <int K>
 __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint32_t *buf, SweepShared &W)
 {
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const WinDesc d0 = a.win[w0];
     const int m = (int)d0.m;
     const int s = (int)(a.win[w0 + 1].x - d0.x);  // the plan gives C >= 2 windows at a constant stride
@@ -2125,13 +2123,21 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         W.mx[0] = W.mx[1] = INT32_MIN;
         W.acc = 0ull;
         W.offc = 0u;
+        W.nwork[0] = W.nwork[1] = 0u;
     }
     block_sync();
+    // the run's points, read from HBM once: grid integers (then keys) in
+    // span, off-grid marks in offb
+    uint32_t *span = buf;                                                // 2 words per point
+    uint8_t *offb = reinterpret_cast<uint8_t *>(buf + 2 * kSweepSpan);  // kSweepSpan bytes
     {
         int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
-        uint32_t off = 0;  // off-grid values are flagged per window below
         for (int i = tid; i < N; i += kBlock) {
+            uint32_t off = 0;
             const int32_t xi = grid_int(X[i], off), yi = grid_int(Y[i], off);
+            span[2 * i] = (uint32_t)xi;
+            span[2 * i + 1] = (uint32_t)yi;
+            offb[i] = off ? 1 : 0;
             mnx = min(mnx, xi);
             mxx = max(mxx, xi);
             mny = min(mny, yi);
@@ -2157,84 +2163,195 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     if ((range >> (32 - ib)) != 0u)
         return false;  // 32-bit keys do not fit
     const uint32_t est = a.estimator;
+    // ownership of the window's points: slot r = index mod R, R = pow2(m + s)
     const int R = (int)(1u << ceil_log2((uint32_t)(m + s)));
     const uint32_t rmask = (uint32_t)R - 1u;
-    uint32_t *ring = buf;                                      // 2 words per slot, R <= kSweepRing
-    uint32_t *lists = buf + 2 * kSweepRing;                    // kSweepShared x K: lists of searched points
-    uint32_t *work = lists + kSweepShared * kMaxK;             // kSweepShared slots to search
-    uint32_t *rec = work + kSweepShared;                       // kSweepShared slots to recount
-    uint32_t *recr = rec + kSweepShared;                       // their radii (2 each)
-    int32_t *recn = reinterpret_cast<int32_t *>(recr + 2 * kSweepShared);  // their counts (2 each)
-
-    // per owned slot (slot tid and tid + 256): the point's state
-    constexpr int Q = kSweepRing / kBlock;
-    uint32_t Lk[Q][K], QX[Q], QY[Q], EX[Q], EY[Q];
-    int NX[Q], NY[Q], WI[Q];
-    bool OFF[Q];
-    auto stage = [&](int j, int q) {
-        uint32_t o = 0;
-        const int32_t xi = grid_int(X[j], o), yi = grid_int(Y[j], o);
-        QX[q] = (uint32_t)(xi - mnx) << ib;
-        QY[q] = (uint32_t)(yi - mny) << ib;
-        ring[2 * (j & (int)rmask)] = QX[q];
-        ring[2 * (j & (int)rmask) + 1] = QY[q];
-        OFF[q] = o != 0u;
-    };
-
-    // ---- the first window, in full
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int r = tid + kBlock * q;
-        OFF[q] = false;
-        if (r < m)
-            stage(r, q);
+    const uint32_t imask = (1u << ib) - 1u;
+    for (int i = tid; i < N; i += kBlock) {
+        span[2 * i] = (uint32_t)((int32_t)span[2 * i] - mnx) << ib;
+        span[2 * i + 1] = (uint32_t)((int32_t)span[2 * i + 1] - mny) << ib;
     }
-    block_sync();
-    long long term = 0;
-    uint32_t offn = 0;
-    {
-        // each owner scans the window for its slots (k+1 keys, itself dropped)
+    // LDS after the span: the step's jobs (slots) and their results (k keys
+    // and two counts each)
+    constexpr int RW = K + 2;
+    constexpr int kSpanWords = 2 * kSweepSpan + kSweepSpan / 4;
+    constexpr int kJobs = (2 * kChunk - kSpanWords) / (RW + 1);
+    const uint32_t *ring = span;  // indexed by run-relative point index
+    constexpr uint32_t kAll = 0xFFFFFFFFu;
+    uint32_t *job = buf + kSpanWords;
+    uint32_t *res = job + kJobs;
+
+    // the ring slot owned by this thread (R <= 256): its point's state
+    const int r = tid;
+    uint32_t Lk[K], QX = 0u, QY = 0u, EX = 0u, EY = 0u;
+    int NX = 0, NY = 0, JI = -1;
+    bool OFF = false;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = tid + kBlock * q;
-            const bool live = r < m;
-            const uint32_t qx = live ? QX[q] : 0u, qy = live ? QY[q] : 0u;
-            uint32_t t[K + 1];
+    for (int e = 0; e < K; ++e)
+        Lk[e] = 0xFFFFFFFFu;
+    auto stage = [&](int j) {
+        QX = ring[2 * j];
+        QY = ring[2 * j + 1];
+        OFF = offb[j] != 0;
+    };
+    block_sync();  // keys in place
+    if (r < m)
+        stage(r);
+
+    int lo = 0;  // the current window is [lo, lo + m)
+    for (int c = 0;; ++c) {
+        // ---- which points search and count in full: all of the first
+        // window; later the added points, the points whose list held a
+        // removed one, and the points whose radii the added points changed
+        int cat = 0;  // 0 empty, 2 in the window, 3 just added
+        uint32_t J;
+        const int j_own = lo + ((r - lo) & (int)rmask);
+        if (c == 0) {
+            cat = r < m ? 3 : 0;
+            JI = r < m ? r : -1;
+            J = (uint32_t)m;
+        } else {
+            const int plo = lo - s;  // the previous window's first point
+            cat = r >= R ? 0 : (j_own < lo ? 0 : (j_own < plo + m ? 2 : (j_own < lo + m ? 3 : 0)));
+            JI = -1;
+            uint32_t ins = 0;
+            bool full = cat == 3;
+            if (cat == 2) {
+                bool stale = false;
 #pragma unroll
-            for (int e = 0; e <= K; ++e)
-                t[e] = 0xFFFFFFFFu;
-            if (__ballot(live) != 0ull) {
-                for (int j = 0; j < m; ++j) {
-                    const uint32_t key = tmax(sad_key(qx, ring[2 * j], (uint32_t)j), sad_key(qy, ring[2 * j + 1], (uint32_t)j));
-                    insert_sorted<K + 1>(t, key);
+                for (int e = 0; e < K; ++e)
+                    stale = stale || (int)(Lk[e] & imask) < lo;
+                if (stale) {
+                    full = true;
+                } else {
+                    for (int j = plo + m; j < lo + m; ++j) {
+                        const uint32_t sl = (uint32_t)j;
+                        const uint32_t key =
+                            tmax(sad_key_v(QX, ring[2 * sl], (uint32_t)j), sad_key_v(QY, ring[2 * sl + 1], (uint32_t)j));
+                        insert_sorted<K>(Lk, key);
+                    }
+                    ins = (uint32_t)s;
+                    uint32_t ex, ey;
+                    sweep_radii<K>(Lk, ring, kAll, ib, QX, QY, est, ex, ey);
+                    if (ex != EX || ey != EY) {
+                        full = true;
+                    } else {
+                        // the same radii: the counts move by the removed and
+                        // added points inside the marginal regions
+                        int dxn = 0, dyn = 0;
+                        for (int j = plo; j < lo; ++j) {
+                            const uint32_t sl = (uint32_t)j;
+                            dxn -= sweep_pred(sad_u32(QX, ring[2 * sl], 0u), ex, est);
+                            dyn -= sweep_pred(sad_u32(QY, ring[2 * sl + 1], 0u), ey, est);
+                        }
+                        for (int j = plo + m; j < lo + m; ++j) {
+                            const uint32_t sl = (uint32_t)j;
+                            dxn += sweep_pred(sad_u32(QX, ring[2 * sl], 0u), ex, est);
+                            dyn += sweep_pred(sad_u32(QY, ring[2 * sl + 1], 0u), ey, est);
+                        }
+                        NX += dxn;
+                        NY += dyn;
+                    }
                 }
-                count_evals_lanes(a, live ? (uint32_t)(m - 1) : 0u);
             }
-            // drop the point's own key (index r, distance 0)
+            if (full) {
+                const uint32_t ji = atomicAdd(&W.nwork[c & 1], 1u);
+                JI = (int)ji;
+                if (ji < (uint32_t)kJobs)
+                    job[ji] = (uint32_t)r;
+            }
+            count_evals_lanes(a, ins);
+            block_sync();  // the job list is complete
+            J = W.nwork[c & 1];
+        }
+        // the next window's counter: its last use (two windows back) ended
+        // at that window's job-list barrier, its next use starts after this
+        // window's last barrier
+        if (tid == 0)
+            W.nwork[(c + 1) & 1] = 0u;
+        // ---- the jobs: groups of kSweepGroup lanes, or each owner alone
+        if (J <= (uint32_t)kJobs) {
+            const uint32_t grp = (uint32_t)tid / kSweepGroup;
+            for (uint32_t jb = grp; jb < J; jb += kBlock / kSweepGroup) {
+                const uint32_t sl = c == 0 ? jb : job[jb];
+                const int jq = lo + (int)((sl - (uint32_t)lo) & rmask);
+                uint32_t t[K];
+                int cx, cy;
+                sweep_group_update<K>(ring, kAll, ib, lo, m, jq, est, t, cx, cy);
+                if ((tid & (kSweepGroup - 1)) == 0) {
 #pragma unroll
-            for (int e = 0; e < K; ++e)
-                Lk[q][e] = t[e] < (uint32_t)r ? t[e] : t[e + 1];
-            if (live) {
-                sweep_radii<K>(Lk[q], ring, rmask, ib, qx, qy, est, EX[q], EY[q]);
-                int cx = 0, cy = 0;
-                for (int j = 0; j < m; ++j) {
-                    if (j == r)
-                        continue;
-                    cx += sweep_pred(sad_u32(qx, ring[2 * j], 0u), EX[q], est);
-                    cy += sweep_pred(sad_u32(qy, ring[2 * j + 1], 0u), EY[q], est);
+                    for (int e = 0; e < K; ++e)
+                        res[jb * RW + e] = t[e];
+                    res[jb * RW + K] = (uint32_t)cx;
+                    res[jb * RW + K + 1] = (uint32_t)cy;
+                    if (a.evals)
+                        atomicAdd(&a.evals[blockIdx.x], (unsigned long long)(m - 1));
                 }
-                NX[q] = cx;
-                NY[q] = cy;
-                if (est != 0 && EX[q] == 0u)
-                    NX[q] = NY[q] = 0;
-                term += est == 0 ? a.psi_fix[NX[q]] + a.psi_fix[NY[q]] : a.psi_fix[NX[q] + 1] + a.psi_fix[NY[q] + 1];
-                offn += OFF[q] ? 1u : 0u;
+            }
+            block_sync();  // the jobs' results are in LDS
+            if (JI >= 0) {
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    Lk[e] = res[JI * RW + e];
+                NX = (int)res[JI * RW + K];
+                NY = (int)res[JI * RW + K + 1];
+                sweep_radii<K>(Lk, ring, kAll, ib, QX, QY, est, EX, EY);
+            }
+        } else {
+            // more jobs than LDS room (many ties on the removed points)
+            const bool need = JI >= 0;
+            if (__ballot(need) != 0ull) {
+                uint32_t t[K];
+#pragma unroll
+                for (int e = 0; e < K; ++e)
+                    t[e] = 0xFFFFFFFFu;
+                for (int j = lo; j < lo + m; ++j) {
+                    const uint32_t sl = (uint32_t)j;
+                    uint32_t key =
+                        tmax(sad_key_v(QX, ring[2 * sl], (uint32_t)j), sad_key_v(QY, ring[2 * sl + 1], (uint32_t)j));
+                    key = j == j_own ? 0xFFFFFFFFu : key;
+                    insert_sorted<K>(t, key);
+                }
+                uint32_t ex, ey;
+                sweep_radii<K>(t, ring, kAll, ib, QX, QY, est, ex, ey);
+                int nx = 0, ny = 0;
+                for (int j = lo; j < lo + m; ++j) {
+                    const uint32_t sl = (uint32_t)j;
+                    if (j != j_own) {
+                        nx += sweep_pred(sad_u32(QX, ring[2 * sl], 0u), ex, est);
+                        ny += sweep_pred(sad_u32(QY, ring[2 * sl + 1], 0u), ey, est);
+                    }
+                }
+                count_evals_lanes(a, need ? (uint32_t)(m - 1) : 0u);
+                if (need) {
+#pragma unroll
+                    for (int e = 0; e < K; ++e)
+                        Lk[e] = t[e];
+                    EX = ex;
+                    EY = ey;
+                    NX = nx;
+                    NY = ny;
+                }
             }
         }
-    }
 
-    for (int c = 0;; ++c) {
-        // ---- window c is complete: its estimate and result
+        // ---- window c: digamma terms; the next window's added points
+        long long term = 0;
+        uint32_t offn = 0;
+        if (cat != 0) {
+            int nx = NX, ny = NY;
+            if (est != 0 && EX == 0u)
+                nx = ny = 0;
+            term = est == 0 ? a.psi_fix[nx] + a.psi_fix[ny] : a.psi_fix[nx + 1] + a.psi_fix[ny + 1];
+            offn = OFF ? 1u : 0u;
+        }
+        const bool more = c + 1 < (int)nwin;
+        if (more) {
+            // they take the slots of points that left before this window
+            const int jn = (lo + s) + ((r - (lo + s)) & (int)rmask);
+            if (r < R && jn >= lo + m && jn < lo + m + s)
+                stage(jn);
+        }
         for (int o = 32; o > 0; o >>= 1) {
             term += __shfl_xor(term, o, 64);
             offn += (uint32_t)__shfl_xor((int)offn, o, 64);
@@ -2244,7 +2361,7 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             if (offn)
                 atomicAdd(&W.offc, offn);
         }
-        block_sync();
+        block_sync();  // sums complete, added points staged
         if (tid == 0) {
             const uint32_t w = w0 + (uint32_t)c;
             const double mi = window_estimate<K>(a, m, (long long)W.acc);
@@ -2255,197 +2372,10 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             store_result(a, qi, compose_result(a.qd[qi], &mi, &fl));
             W.acc = 0ull;
             W.offc = 0u;
-            W.nwork = 0u;
-            W.nrec = 0u;
         }
-        if (c + 1 >= (int)nwin)
+        if (!more)
             break;
-        term = 0;
-        offn = 0;
-
-        // ---- step to window c + 1: points [lo, nlo) leave, [lo + m, lo + m + s) enter
-        const int lo = c * s, nlo = lo + s;
-        int cat[Q];  // 0 empty, 1 leaving, 2 remaining, 3 entering
-        int J[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = tid + kBlock * q;
-            const int j = lo + ((r - lo) & (int)rmask);
-            J[q] = j;
-            cat[q] = r >= R ? 0 : (j < nlo ? 1 : (j < lo + m ? 2 : (j < lo + m + s ? 3 : 0)));
-            if (cat[q] == 3)
-                stage(j, q);
-        }
-        block_sync();  // entering points staged; counters cleared
-        // a point keeps its list unless it holds a leaving point; the others
-        // insert the entering points' keys
-        uint32_t ins = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            WI[q] = -1;
-            bool search = cat[q] == 3;
-            if (cat[q] == 2) {
-                const uint32_t imask = (1u << ib) - 1u;
-                bool stale = false;
-#pragma unroll
-                for (int e = 0; e < K; ++e)
-                    stale = stale || (int)(Lk[q][e] & imask) < nlo;
-                if (stale) {
-                    search = true;
-                } else {
-                    for (int j = lo + m; j < lo + m + s; ++j) {
-                        const uint32_t sl = (uint32_t)j & rmask;
-                        const uint32_t key =
-                            tmax(sad_key_v(QX[q], ring[2 * sl], (uint32_t)j), sad_key_v(QY[q], ring[2 * sl + 1], (uint32_t)j));
-                        insert_sorted<K>(Lk[q], key);
-                    }
-                    ins += (uint32_t)s;
-                }
-            }
-            if (search) {
-                const uint32_t wi = atomicAdd(&W.nwork, 1u);
-                WI[q] = (int)wi;
-                if (wi < (uint32_t)kSweepShared)
-                    work[wi] = (uint32_t)(tid + kBlock * q);
-            }
-        }
-        count_evals_lanes(a, ins);
-        block_sync();
-        const uint32_t nwork = W.nwork;
-        if (nwork <= (uint32_t)kSweepShared) {
-            for (uint32_t wi = (uint32_t)wave; wi < nwork; wi += kBlock / 64) {
-                const uint32_t r = work[wi];
-                const int j = nlo + (int)((r - (uint32_t)nlo) & rmask);
-                uint32_t t[K];
-                sweep_wave_search<K>(ring, rmask, nlo, m, j, ring[2 * r], ring[2 * r + 1], t);
-                if ((tid & 63) == 0) {
-#pragma unroll
-                    for (int e = 0; e < K; ++e)
-                        lists[wi * K + e] = t[e];
-                }
-            }
-            count_evals(a, (int)((nwork + (kBlock / 64) - 1 - (uint32_t)wave) / (kBlock / 64)), m - 1);
-            block_sync();
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (WI[q] >= 0) {
-#pragma unroll
-                    for (int e = 0; e < K; ++e)
-                        Lk[q][e] = lists[WI[q] * K + e];
-                }
-        } else {
-            // many searches at once (ties on the removed points): each owner alone
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const bool need = WI[q] >= 0;
-                if (__ballot(need) == 0ull)
-                    continue;
-                uint32_t t[K];
-#pragma unroll
-                for (int e = 0; e < K; ++e)
-                    t[e] = 0xFFFFFFFFu;
-                for (int j = nlo; j < nlo + m; ++j) {
-                    const uint32_t sl = (uint32_t)j & rmask;
-                    uint32_t key =
-                        tmax(sad_key_v(QX[q], ring[2 * sl], (uint32_t)j), sad_key_v(QY[q], ring[2 * sl + 1], (uint32_t)j));
-                    key = j == J[q] ? 0xFFFFFFFFu : key;
-                    insert_sorted<K>(t, key);
-                }
-                count_evals_lanes(a, need ? (uint32_t)(m - 1) : 0u);
-                if (need) {
-#pragma unroll
-                    for (int e = 0; e < K; ++e)
-                        Lk[q][e] = t[e];
-                }
-            }
-        }
-        // ---- radii and counts of the new window
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            WI[q] = -1;
-            if (cat[q] != 2 && cat[q] != 3)
-                continue;
-            uint32_t ex, ey;
-            sweep_radii<K>(Lk[q], ring, rmask, ib, QX[q], QY[q], est, ex, ey);
-            if (cat[q] == 2 && ex == EX[q] && ey == EY[q]) {
-                // Lemmas 3-4: the same radii, counts move by the leaving and
-                // entering points inside the marginal regions
-                int dxn = 0, dyn = 0;
-                for (int j = lo; j < nlo; ++j) {
-                    const uint32_t sl = (uint32_t)j & rmask;
-                    dxn -= sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), ex, est);
-                    dyn -= sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), ey, est);
-                }
-                for (int j = lo + m; j < lo + m + s; ++j) {
-                    const uint32_t sl = (uint32_t)j & rmask;
-                    dxn += sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), ex, est);
-                    dyn += sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), ey, est);
-                }
-                NX[q] += dxn;
-                NY[q] += dyn;
-            } else {
-                EX[q] = ex;
-                EY[q] = ey;
-                const uint32_t ri = atomicAdd(&W.nrec, 1u);
-                WI[q] = (int)ri;
-                if (ri < (uint32_t)kSweepShared) {
-                    rec[ri] = (uint32_t)(tid + kBlock * q);
-                    recr[2 * ri] = ex;
-                    recr[2 * ri + 1] = ey;
-                }
-            }
-        }
-        block_sync();
-        const uint32_t nrec = W.nrec;
-        if (nrec <= (uint32_t)kSweepShared) {
-            for (uint32_t ri = (uint32_t)wave; ri < nrec; ri += kBlock / 64) {
-                const uint32_t r = rec[ri];
-                const int j = nlo + (int)((r - (uint32_t)nlo) & rmask);
-                int cx, cy;
-                sweep_wave_count(ring, rmask, nlo, m, j, ring[2 * r], ring[2 * r + 1], recr[2 * ri], recr[2 * ri + 1],
-                                 est, cx, cy);
-                if ((tid & 63) == 0) {
-                    recn[2 * ri] = cx;
-                    recn[2 * ri + 1] = cy;
-                }
-            }
-            block_sync();
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (WI[q] >= 0) {
-                    NX[q] = recn[2 * WI[q]];
-                    NY[q] = recn[2 * WI[q] + 1];
-                }
-        } else {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const bool need = WI[q] >= 0;
-                if (__ballot(need) == 0ull)
-                    continue;
-                int cx = 0, cy = 0;
-                for (int j = nlo; j < nlo + m; ++j) {
-                    const uint32_t sl = (uint32_t)j & rmask;
-                    if (j != J[q]) {
-                        cx += sweep_pred(sad_u32(QX[q], ring[2 * sl], 0u), EX[q], est);
-                        cy += sweep_pred(sad_u32(QY[q], ring[2 * sl + 1], 0u), EY[q], est);
-                    }
-                }
-                if (need) {
-                    NX[q] = cx;
-                    NY[q] = cy;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (cat[q] != 2 && cat[q] != 3)
-                continue;
-            int nx = NX[q], ny = NY[q];
-            if (est != 0 && EX[q] == 0u)
-                nx = ny = 0;
-            term += est == 0 ? a.psi_fix[nx] + a.psi_fix[ny] : a.psi_fix[nx + 1] + a.psi_fix[ny + 1];
-            offn += OFF[q] ? 1u : 0u;
-        }
+        lo += s;
     }
     return true;
 }
@@ -2604,6 +2534,110 @@ __global__ void validate_kernel(const float *v, uint64_t n, unsigned long long *
 }
 
 // --------------------------------------------------------------------------
+// window entropy (Section 5.4: the denominator of the normalised MI)
+// --------------------------------------------------------------------------
+// H_w is the entropy of the window's empirical distribution of pairs: with
+// c_v the number of points equal to the pair v in both coordinates,
+//   H_w = - sum_v (c_v/m) ln(c_v/m) = ln m - (1/m) sum_i ln c_(i),
+// the last sum over the points, c_(i) the multiplicity of point i's pair.
+// One workgroup per query (grid-stride): each wanted window's pairs become
+// 64-bit keys (float bits of x above those of y, -0 folded into +0), sorted
+// in LDS by a bitonic network; each point then finds its run of equal keys
+// by two binary searches.  The ln c terms are summed in 2^-44 fixed point,
+// so the sum does not depend on the order of the additions.
+
+__device__ __forceinline__ uint32_t pair_bits(float v)
+{
+    const uint32_t b = __float_as_uint(v);
+    return (b << 1) == 0u ? 0u : b;  // +0 and -0 are one value
+}
+
+// Ascending bitonic sort of k[0..P), P a power of two, by the workgroup.
+__device__ void bitonic_u64(unsigned long long *k, uint32_t P)
+{
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            block_sync();
+            for (uint32_t t = threadIdx.x; t < (P >> 1); t += kBlock) {
+                const uint32_t lo = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u));
+                const unsigned long long u = k[lo], v = k[lo + stride];
+                if ((u > v) == ((lo & size) == 0u)) {
+                    k[lo] = v;
+                    k[lo + stride] = u;
+                }
+            }
+        }
+    }
+    block_sync();
+}
+
+// First index in k[0..n) whose key is not below v (upper: above v).
+__device__ __forceinline__ uint32_t key_bound(const unsigned long long *k, uint32_t n, unsigned long long v,
+                                              bool upper)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (upper ? k[mid] <= v : k[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ double window_entropy(const WinDesc &d, unsigned long long *key, long long *s_part)
+{
+    const uint32_t m = d.m;
+    const uint32_t P = 1u << ceil_log2(m > 1u ? m : 2u);
+    block_sync();  // the previous window's keys are no longer read
+    for (uint32_t i = threadIdx.x; i < P; i += kBlock)
+        key[i] = i < m ? ((unsigned long long)pair_bits(d.x[i]) << 32) | pair_bits(d.y[i]) : ~0ull;
+    bitonic_u64(key, P);
+    long long part = 0;
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+        const unsigned long long v = key[i];
+        const uint32_t c = key_bound(key, m, v, true) - key_bound(key, m, v, false);
+        part += c > 1u ? (long long)rint(log((double)c) * 0x1p44) : 0ll;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        part += __shfl_xor(part, o, 64);
+    if ((threadIdx.x & 63u) == 0u)
+        s_part[threadIdx.x >> 6] = part;
+    block_sync();
+    long long S = 0;
+    for (int v = 0; v < kBlock / 64; ++v)
+        S += s_part[v];
+    return log((double)m) - (double)S * 0x1p-44 / (double)m;
+}
+
+__global__ __launch_bounds__(kBlock) void entropy_kernel(EntropyArgs a)
+{
+    __shared__ unsigned long long key[kMaxWindow];
+    __shared__ long long s_part[kBlock / 64];
+    const double nan = __builtin_nan("");
+    for (uint32_t q = blockIdx.x; q < a.n_query; q += gridDim.x) {
+        const QDesc qd = a.qd[q];
+        for (uint32_t r = 0; r < 3u; ++r) {
+            if (r >= qd.nwin) {
+                if (a.hres && threadIdx.x == 0)
+                    a.hres[3u * q + r] = nan;
+                continue;
+            }
+            if (!a.hres && r != 1u)
+                continue;  // only the extension's entropy is wanted
+            const double h = window_entropy(a.win[qd.win0 + r], key, s_part);
+            if (threadIdx.x == 0) {
+                if (a.hres)
+                    a.hres[3u * q + r] = h;
+                if (r == 1u && a.set_tau)
+                    a.qd[q].tau_eff = a.tau * h;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // host-side launchers
 // --------------------------------------------------------------------------
 
@@ -2636,6 +2670,15 @@ hipError_t launch_clear(const LaunchArgs &a, hipStream_t s)
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(clear_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_entropy(const EntropyArgs &a, hipStream_t s)
+{
+    if (a.n_query == 0)
+        return hipSuccess;
+    const uint32_t blocks = a.n_query < 65536u ? a.n_query : 65536u;
+    hipLaunchKernelGGL(entropy_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

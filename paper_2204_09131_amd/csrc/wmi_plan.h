@@ -50,11 +50,14 @@ inline uint32_t plan_pow2(uint32_t v)
 // m + s <= kSweepRing, kSweepStrideDiv s <= m) go to sweep items of
 // kSweepWindows windows (the last one or two items of a run share its
 // remainder, never leaving one window alone).  Reuse (triple and sweep items)
-// is off with fuse_triples false.
+// is off with fuse_triples false.  tune (null: defaults) caps windows per
+// local item, triples per triple item and windows per sweep item by window
+// size.
 inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wquery, uint64_t count,
                        bool plain, Plan &out, bool fuse_triples = true, const std::vector<uint64_t> *wx = nullptr,
-                       const std::vector<uint64_t> *wy = nullptr)
+                       const std::vector<uint64_t> *wy = nullptr, const Tuning *tune = nullptr)
 {
+    const Tuning T = tune ? *tune : default_tuning();
     const uint64_t n_win = wm.size();
     out = Plan();
     out.wsorted.assign(n_win, 0);
@@ -67,9 +70,10 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         uint32_t start = 0, n = 0, slots = 0, maxm = 0;
         uint64_t cost = 0;
     } cur;
-    auto fits = [](const Cur &c, uint32_t m) {
+    auto fits = [&T](const Cur &c, uint32_t m) {
         uint32_t maxm = std::max(std::max(c.maxm, m), 2u);
-        return c.n + 1 <= (uint32_t)kLocalWindows && c.slots + ((m + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
+        const uint32_t cap = std::min<uint32_t>(std::max(T.local_windows[local_bucket(maxm)], 1u), kLocalWindows);
+        return c.n + 1 <= cap && c.slots + ((m + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
                (c.n + 1) * plan_pow2(maxm) <= (uint32_t)kLocalSort;
     };
     auto add = [](Cur &c, uint32_t w, uint32_t m) {
@@ -88,9 +92,10 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
         cur = Cur();
     };
     Cur tri;  // the open triple item: n triples from window start
-    auto fits_tri = [](const Cur &c, uint32_t mu) {
+    auto fits_tri = [&T](const Cur &c, uint32_t mu) {
         uint32_t maxm = std::max(std::max(c.maxm, mu), 2u);
-        return c.n + 1 <= (uint32_t)kTripleMax && c.slots + ((mu + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
+        const uint32_t cap = std::min<uint32_t>(std::max(T.triples[local_bucket(maxm)], 1u), kTripleMax);
+        return c.n + 1 <= cap && c.slots + ((mu + 1u) & ~1u) <= (uint32_t)kLocalSlots &&
                (c.n + 1) * plan_pow2(maxm) <= (uint32_t)kLocalSort;
     };
     auto close_tri = [&]() {
@@ -117,7 +122,8 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
             const int64_t dx = (int64_t)((*wx)[w0 + 1] - (*wx)[w0]), dy = (int64_t)((*wy)[w0 + 1] - (*wy)[w0]);
             const int64_t s = dx / (int64_t)sizeof(float);
             if (dx == dy && dx > 0 && dx % (int64_t)sizeof(float) == 0 && m >= (uint32_t)kSweepMinM &&
-                (int64_t)m + s <= kSweepRing && kSweepStrideDiv * s <= (int64_t)m) {
+                (int64_t)m + s <= kSweepRing && kSweepStrideDiv * s <= (int64_t)m &&
+                T.sweep_windows[sweep_bucket(m)] >= 2) {
                 uint64_t e = w0 + 1;
                 while (e + 1 < n_win && single(e + 1) && wm[e + 1] == m && (*wx)[e + 1] - (*wx)[e] == (uint64_t)dx &&
                        (*wy)[e + 1] - (*wy)[e] == (uint64_t)dy)
@@ -125,10 +131,14 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
                 close();
                 close_tri();
                 uint64_t rest = e + 1 - w0;
+                // windows per item: the tuned count, within 255 and a span
+                // of kSweepSpan points
+                const uint64_t C = std::min<uint64_t>(std::min<uint64_t>(T.sweep_windows[sweep_bucket(m)], 255),
+                                                      (uint64_t)(kSweepSpan - (int64_t)m) / (uint64_t)s + 1);
                 while (rest > 0) {
-                    const uint64_t c = rest <= (uint64_t)kSweepWindows
-                                           ? rest
-                                           : (rest == (uint64_t)kSweepWindows + 1 ? rest / 2 : (uint64_t)kSweepWindows);
+                    // never leave one window alone: C + 1 windows split in
+                    // two halves (three go together)
+                    const uint64_t c = rest <= C ? rest : (rest == C + 1 ? (rest >= 4 ? rest / 2 : rest) : C);
                     out.items.push_back(Item{w, kItemSweep | (uint32_t)c});
                     out.cost.push_back((uint64_t)m * m + c * (uint64_t)m * (uint64_t)(16 + 2 * s));
                     w += (uint32_t)c;
@@ -253,10 +263,12 @@ inline void plan_queue(const Plan &P, const std::vector<uint32_t> &wm, std::vect
 
 // Serving: local windows per item for a run of windows of m points (the
 // local-item limits above, every window of the run the same size).
-inline uint32_t plan_local_per_item(uint32_t m)
+inline uint32_t plan_local_per_item(uint32_t m, const Tuning *tune = nullptr)
 {
+    const Tuning T = tune ? *tune : default_tuning();
     const uint32_t even = (m + 1u) & ~1u;
-    const uint32_t n = std::min<uint32_t>((uint32_t)kLocalWindows, (uint32_t)kLocalSlots / even);
+    const uint32_t cap = std::min<uint32_t>(std::max(T.local_windows[local_bucket(std::max(m, 2u))], 1u), kLocalWindows);
+    const uint32_t n = std::min<uint32_t>(cap, (uint32_t)kLocalSlots / even);
     return std::max(1u, std::min(n, (uint32_t)kLocalSort / plan_pow2(std::max(m, 2u))));
 }
 
@@ -265,7 +277,7 @@ inline uint32_t plan_local_per_item(uint32_t m)
 // and items: all prep items first, then local items, then split items,
 // larger windows first within each.  Returns the queue length; *split
 // receives the sorted-marginal points (sum of m over split windows).
-inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split)
+inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split, const Tuning *tune = nullptr)
 {
     std::vector<uint32_t> order(n);
     uint32_t win0 = 0;
@@ -289,7 +301,7 @@ inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split)
     for (uint32_t i : order)
         if (pd[i].m <= (uint32_t)kLocalSlots) {
             pd[i].item0 = q;
-            pd[i].per_item = plan_local_per_item(pd[i].m);
+            pd[i].per_item = plan_local_per_item(pd[i].m, tune);
             q += (pd[i].count + pd[i].per_item - 1) / pd[i].per_item;
         }
     for (uint32_t i : order)

@@ -36,6 +36,7 @@ using namespace wmi;
 static_assert(sizeof(wmi_query) == 32, "wmi_query layout");
 static_assert(sizeof(wmi_result) == 32 && sizeof(Result) == 32, "result layout");
 static_assert(sizeof(WinDesc) == 32 && sizeof(Item) == 8 && sizeof(QDesc) == 16, "descriptors");
+static_assert(sizeof(wmi_tuning) == sizeof(Tuning), "tuning layout");
 
 namespace wmi {
 
@@ -93,11 +94,14 @@ struct wmi_batch {
     size_t host_bytes = 0;
     size_t desc_bytes = 0;  // uploaded prefix
     LaunchArgs args{};
+    EntropyArgs eargs{};   // the entropy pass, when eargs.n_query > 0
+    size_t res_bytes = 0;  // downloaded: results, error word, entropies
     uint32_t grid = 0;
     std::vector<uint32_t> win_first_item;  // plain form: first item of each window
     std::vector<int32_t> win_prep;         // plain form: prep-list entry of a split window, or -1
     Result *h_res = nullptr;
     Result *d_res = nullptr;
+    const double *h_hres = nullptr;  // entropies in the host buffer, or null
     RunEvents slot[kSlots];
     hipEvent_t ev_end = nullptr;  // recorded after the completion callback of the latest run
     hipGraph_t graph = nullptr;
@@ -205,6 +209,8 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
     HIPCHK(st, launch_clear(a, s));
     if (ev)
         HIPCHK(st, hipEventRecord(ev->p0, s));
+    // window entropies first: the noise thresholds of tau_normalize 2 need them
+    HIPCHK(st, launch_entropy(b->eargs, s));
     if (b->params.flags & WMI_SUBMIT_PLAIN) {
         // baseline form: every window is its own prep launch and main launch
         for (uint32_t w = 0; w < a.n_win; ++w) {
@@ -230,8 +236,7 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
         if (ev)
             HIPCHK(st, hipEventRecord(ev->m1, s));
     }
-    HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->count * sizeof(Result) + sizeof(uint32_t),
-                              hipMemcpyDeviceToHost, s));
+    HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->res_bytes, hipMemcpyDeviceToHost, s));
     return WMI_OK;
 }
 
@@ -295,7 +300,8 @@ int run_batch(wmi_batch *b, hipStream_t s, int mode)
             release_locked(b);
         return rc;
     }
-    b->stats.launches = (b->params.flags & WMI_SUBMIT_PLAIN) ? 1 + 2ull * b->args.n_win : 3;
+    b->stats.launches = ((b->params.flags & WMI_SUBMIT_PLAIN) ? 1 + 2ull * b->args.n_win : 3) +
+                        (b->eargs.n_query ? 1 : 0);
     return WMI_OK;
 }
 
@@ -420,6 +426,43 @@ int wmi_store_create(const wmi_store_desc *desc, wmi_store **out)
 }
 
 int wmi_batch_destroy(wmi_batch *b);
+
+int wmi_store_set_tuning(wmi_store *st, const wmi_tuning *t)
+{
+    if (!st)
+        return fail(WMI_EINVAL, "wmi_store_set_tuning: null store");
+    Tuning v = default_tuning();
+    if (t) {
+        std::memcpy(&v, t, sizeof v);
+        for (int b = 0; b < 5; ++b) {
+            if (v.local_windows[b] < 1 || v.local_windows[b] > (uint32_t)kLocalWindows)
+                return fail(WMI_EINVAL, "wmi_store_set_tuning: local_windows[%d] = %u outside 1..%d", b,
+                            v.local_windows[b], kLocalWindows);
+            if (v.triples[b] < 1 || v.triples[b] > (uint32_t)kTripleMax)
+                return fail(WMI_EINVAL, "wmi_store_set_tuning: triples[%d] = %u outside 1..%d", b, v.triples[b],
+                            kTripleMax);
+        }
+        for (int b = 0; b < 3; ++b) {
+            if (v.sweep_windows[b] < 1 || v.sweep_windows[b] > 255)
+                return fail(WMI_EINVAL, "wmi_store_set_tuning: sweep_windows[%d] = %u outside 1..255", b,
+                            v.sweep_windows[b]);
+            if (v.stragglers[b] > 128)
+                return fail(WMI_EINVAL, "wmi_store_set_tuning: stragglers[%d] = %u above 128", b, v.stragglers[b]);
+        }
+    }
+    std::lock_guard<std::mutex> lk(st->mu);
+    st->tune = v;
+    return WMI_OK;
+}
+
+int wmi_store_get_tuning(wmi_store *st, wmi_tuning *out)
+{
+    if (!st || !out)
+        return fail(WMI_EINVAL, "wmi_store_get_tuning: null argument");
+    std::lock_guard<std::mutex> lk(st->mu);
+    std::memcpy(out, &st->tune, sizeof *out);
+    return WMI_OK;
+}
 
 int wmi_store_destroy(wmi_store *st)
 {
@@ -570,9 +613,9 @@ static int validate_params(const wmi_params *p)
         return fail(WMI_EINVAL, "k = %u outside 1..%d", p->k, WMI_MAX_K);
     if (p->estimator > 1)
         return fail(WMI_EINVAL, "estimator %u unknown (0 or 1)", p->estimator);
-    if (p->tau_normalize > 1)
-        return fail(WMI_EINVAL, "tau_normalize must be 0 or 1");
-    if (p->flags & ~(WMI_SUBMIT_NONBLOCKING | WMI_SUBMIT_PLAIN | WMI_SUBMIT_NO_REUSE))
+    if (p->tau_normalize > 2)
+        return fail(WMI_EINVAL, "tau_normalize must be 0, 1 or 2");
+    if (p->flags & ~(WMI_SUBMIT_NONBLOCKING | WMI_SUBMIT_PLAIN | WMI_SUBMIT_NO_REUSE | WMI_SUBMIT_ENTROPY))
         return fail(WMI_EINVAL, "unknown submit flags 0x%x", p->flags);
     if (!std::isfinite(p->tau))
         return fail(WMI_EINVAL, "tau must be finite");
@@ -637,13 +680,14 @@ struct BatchBuild {
     std::vector<uint64_t> wstart;  // windows in query order (a triple: base, extension, union)
     std::vector<uint32_t> wm, wquery, used;
     std::vector<uint64_t> wx, wy;  // address of each window's first x and y value
+    Tuning tune;
     uint64_t pairs = 0, n_win = 0, n_items = 0, n_prep = 0;
     bool plain = false;
     Plan plan;
     std::vector<Item> queue;
     size_t o_win = 0, o_item = 0, o_qd = 0, o_prep = 0, desc_bytes = 0, o_sorted = 0, o_acc = 0, o_wdone = 0,
-           o_qdone = 0, o_counter = 0, o_wmi = 0, o_wflags = 0, o_ready = 0, o_res = 0, res_bytes = 0,
-           dev_bytes = 0;
+           o_qdone = 0, o_counter = 0, o_wmi = 0, o_wflags = 0, o_ready = 0, o_res = 0, o_hres = 0,
+           res_bytes = 0, dev_bytes = 0;
 };
 
 int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, BatchBuild &B)
@@ -651,6 +695,7 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
     {
         std::lock_guard<std::mutex> lk(st->mu);
         B.ser = st->series;
+        B.tune = st->tune;
     }
     B.wstart.reserve(count);
     B.wm.reserve(count);
@@ -680,7 +725,7 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
 
     // ---- work items ---------------------------------------------------------
     B.plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
-    plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE), &B.wx, &B.wy);
+    plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE), &B.wx, &B.wy, &B.tune);
     if (!B.plain)
         plan_queue(B.plan, B.wm, B.queue);
     B.n_items = B.plain ? B.plan.items.size() : B.queue.size();
@@ -705,8 +750,12 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
     B.o_wflags = align_up(B.o_wmi + B.n_win * sizeof(double), A);
     B.o_ready = align_up(B.o_wflags + B.n_win * sizeof(uint32_t), A);
     B.o_res = align_up(B.o_ready + B.n_win * sizeof(uint32_t), A);
-    // results and the error word are downloaded together
+    // results, the error word and the entropies are downloaded together
     B.res_bytes = count * sizeof(Result) + sizeof(uint32_t);
+    if (p->flags & WMI_SUBMIT_ENTROPY) {
+        B.o_hres = align_up(B.o_res + B.res_bytes, 8);
+        B.res_bytes = B.o_hres - B.o_res + 3 * count * sizeof(double);
+    }
     B.dev_bytes = align_up(B.o_res + B.res_bytes, A);
     return WMI_OK;
 }
@@ -737,7 +786,8 @@ void write_descriptors(const BatchBuild &B, const wmi_query *qs, uint64_t count,
             ++i;
         }
         hq[t].nwin = nw;
-        hq[t].tau_eff = p->tau_normalize ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
+        // tau_normalize 2: the entropy pass writes tau * H(w_d) here
+        hq[t].tau_eff = p->tau_normalize == 1 ? p->tau * std::log((double)qs[t].ext_len) : p->tau;
     }
     std::copy(B.plan.prep_list.begin(), B.plan.prep_list.end(), hp);
     if (B.plain)
@@ -777,6 +827,25 @@ void set_args(const BatchBuild &B, const wmi_store *st, const wmi_params *p, uin
     a.estimator = p->estimator;
     a.persistent = 1;
     a.win_begin = 0;
+    for (int i = 0; i < 3; ++i)
+        a.strag[i] = B.tune.stragglers[i];
+}
+
+// The entropy pass over a device buffer laid out as B: all windows' entropies
+// into hres when given; the extensions' only (the thresholds) otherwise.  No
+// pass (n_query 0) when neither is wanted.
+void set_entropy_args(const BatchBuild &B, const wmi_params *p, uint64_t count, char *dev, double *hres,
+                      EntropyArgs &e)
+{
+    e = EntropyArgs{};
+    if (!hres && p->tau_normalize != 2)
+        return;
+    e.win = reinterpret_cast<const WinDesc *>(dev + B.o_win);
+    e.qd = reinterpret_cast<QDesc *>(dev + B.o_qd);
+    e.hres = hres;
+    e.tau = p->tau;
+    e.n_query = (uint32_t)count;
+    e.set_tau = p->tau_normalize == 2 ? 1u : 0u;
 }
 
 }  // namespace
@@ -866,6 +935,13 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     set_args(B, st, p, count, b->dev, reinterpret_cast<Result *>(b->dev + B.o_res),
              reinterpret_cast<uint32_t *>(b->dev + B.o_res + count * sizeof(Result)), a);
     b->d_res = a.res;
+    b->res_bytes = B.res_bytes;
+    double *d_hres = nullptr;
+    if (p->flags & WMI_SUBMIT_ENTROPY) {
+        d_hres = reinterpret_cast<double *>(b->dev + B.o_hres);
+        b->h_hres = reinterpret_cast<const double *>(b->host + desc_bytes + (B.o_hres - B.o_res));
+    }
+    set_entropy_args(B, p, count, b->dev, d_hres, b->eargs);
     int occ = main_occupancy(p->k);
     uint64_t slots = (uint64_t)st->cu_count * (uint64_t)occ;
     b->grid = (uint32_t)std::min<uint64_t>(B.n_items, slots);
@@ -897,7 +973,7 @@ int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const
     if (int rc = validate_params(p))
         return rc;
     if (p->flags)
-        return fail(WMI_EINVAL, "wmi_submit_noalloc: flags must be 0");
+        return fail(WMI_EINVAL, "wmi_submit_noalloc: flags must be 0");  // entropies are not returned here
     if (count > 0xFFFFFFF0ull)
         return fail(WMI_EINVAL, "wmi_submit_noalloc: too many queries in one call");
     if (int rc = check_poison(st))
@@ -942,6 +1018,8 @@ int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const
     LaunchArgs a;
     set_args(B, st, p, count, dev, reinterpret_cast<Result *>(d_results), reinterpret_cast<uint32_t *>(dev + B.o_res),
              a);
+    EntropyArgs ea;
+    set_entropy_args(B, p, count, dev, nullptr, ea);
     const uint32_t grid =
         (uint32_t)std::min<uint64_t>(B.n_items, (uint64_t)st->cu_count * (uint64_t)main_occupancy(p->k));
     hipStream_t s = stream ? (hipStream_t)stream : st->stream;
@@ -949,6 +1027,8 @@ int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const
     hipError_t e = hipMemcpyAsync(dev, host.data(), B.desc_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_clear(a, s);  // counters, sums, flags and the error word start at zero
+    if (e == hipSuccess)
+        e = launch_entropy(ea, s);
     if (e == hipSuccess)
         e = launch_main(a, grid, s);
     if (e == hipSuccess)
@@ -988,6 +1068,20 @@ int wmi_read(wmi_batch *b, wmi_result *out)
         return rc;
     if (b->count)
         std::memcpy(out, b->h_res, b->count * sizeof(Result));
+    return WMI_OK;
+}
+
+int wmi_read_entropy(wmi_batch *b, double *host_out)
+{
+    if (!b || (!host_out && b->count))
+        return fail(WMI_EINVAL, "wmi_read_entropy: null argument");
+    if (!b->h_hres)
+        return fail(WMI_ESTATE, "wmi_read_entropy: the batch was submitted without WMI_SUBMIT_ENTROPY");
+    DeviceGuard g(b->st->device);
+    if (int rc = finish_if_done(b, true, -1))
+        return rc;
+    if (b->count)
+        std::memcpy(host_out, b->h_hres, b->count * 3 * sizeof(double));
     return WMI_OK;
 }
 

@@ -40,6 +40,7 @@ uint64_t triple_pairs(uint64_t m, uint64_t e)
 
 struct Eval {
     double mi = 0.0;   // I(w)
+    double h = 0.0;    // H(w) when the batch computed entropies
     bool noise = false;
 };
 
@@ -53,6 +54,8 @@ int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> 
     const uint64_t chunk = std::max<uint64_t>(1, std::min(kChunkQueries, kChunkPoints / per_q));
     std::vector<wmi_query> q;
     std::vector<wmi_result> r;
+    std::vector<double> h;
+    const bool ent = (prm.flags & WMI_SUBMIT_ENTROPY) != 0;
     for (uint64_t i0 = 0; i0 < starts.size(); i0 += chunk) {
         const uint64_t n = std::min<uint64_t>(chunk, starts.size() - i0);
         q.assign(n, wmi_query());
@@ -71,11 +74,16 @@ int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> 
             return rc;
         r.assign(n, wmi_result());
         int rc = wmi_read(bt, r.data());
+        if (rc == WMI_OK && ent) {
+            h.assign(3 * n, 0.0);
+            rc = wmi_read_entropy(bt, h.data());
+        }
         (void)wmi_batch_destroy(bt);
         if (rc)
             return rc;
         for (uint64_t i = 0; i < n; ++i) {
             out[i0 + i].mi = triple ? r[i].mi_union : r[i].mi_base;
+            out[i0 + i].h = ent ? h[3 * i + (triple ? 2 : 0)] : 0.0;
             out[i0 + i].noise = (r[i].flags & WMI_F_NOISE) != 0;
         }
         stats.batches++;
@@ -106,7 +114,7 @@ extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
     *n_out = 0;
     if (p->s_min < 2 || p->s_min > p->s_max || p->s_max > (uint32_t)WMI_MAX_WINDOW || p->flags)
         return fail(WMI_EINVAL, "wmi_td_search: need 2 <= s_min <= s_max <= %d and flags 0", WMI_MAX_WINDOW);
-    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 1)
+    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 2)
         return fail(WMI_EINVAL, "wmi_td_search: bad k, estimator or normalize");
     uint64_t na = 0, nb = 0;
     if (int rc = wmi_series_length(st, a, &na))
@@ -122,7 +130,7 @@ extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
     prm.estimator = p->estimator;
     prm.tau = p->tau;
     prm.tau_normalize = p->normalize;
-    prm.flags = 0;
+    prm.flags = p->normalize == 2 ? WMI_SUBMIT_ENTROPY : 0u;  // sigma * H(w) needs every window's H
 
     wmi_search_stats stats{};
     std::vector<wmi_window> found;
@@ -136,7 +144,7 @@ extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
         stats.layers++;
         const uint32_t delta = std::max(1u, s_w / div);
         const bool triple = p->p > 0 && delta < s_w;
-        const double thr = p->normalize ? p->sigma * std::log((double)s_w) : p->sigma;
+        const double thr = p->normalize == 1 ? p->sigma * std::log((double)s_w) : p->sigma;
         // speculative pass: every grid window of every partition
         std::vector<Walk> walks;
         std::vector<uint64_t> starts;
@@ -179,7 +187,7 @@ extern "C" int wmi_td_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                         e = &it->second;
                     }
                     stats.windows_visited++;
-                    if (e->mi >= thr) {
+                    if (e->mi >= (p->normalize == 2 ? p->sigma * e->h : thr)) {
                         found.push_back(wmi_window{wk.w, s_w, layer, e->mi});
                         wk.corr.push_back({wk.w, wk.w + s_w});
                         wk.w += s_w;
@@ -269,9 +277,11 @@ uint64_t bu_pick(uint64_t seed, uint64_t chunk, uint64_t i)
 }
 
 int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params &prm, std::vector<wmi_result> &r,
-                wmi_search_stats &stats)
+                std::vector<double> &h, wmi_search_stats &stats)
 {
     r.assign(q.size(), wmi_result());
+    const bool ent = (prm.flags & WMI_SUBMIT_ENTROPY) != 0;
+    h.assign(ent ? 3 * q.size() : 0, 0.0);
     size_t i0 = 0;
     while (i0 < q.size()) {
         size_t i1 = i0;
@@ -284,6 +294,8 @@ int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params
         if (int rc = wmi_submit(st, q.data() + i0, i1 - i0, &prm, nullptr, &bt))
             return rc;
         int rc = wmi_read(bt, r.data() + i0);
+        if (rc == WMI_OK && ent)
+            rc = wmi_read_entropy(bt, h.data() + 3 * i0);
         (void)wmi_batch_destroy(bt);
         if (rc)
             return rc;
@@ -310,6 +322,7 @@ struct Walker {
     bool climbing = false, done = false;
     uint64_t ws = 0, we = 0;        // current window [ws, we)
     double iw = 0.0;
+    double hw = 0.0;                // H(w) when the thresholds take entropies
     std::vector<double> hist;
     uint32_t idle = 0, lrun = 0, rrun = 0;
     bool loff = false, roff = false;
@@ -344,7 +357,7 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
         p->history < 1 || p->flags || p->reserved)
         return fail(WMI_EINVAL, "wmi_bu_search: need 2 <= s_min <= s_max <= %d, delta >= 1, history >= 1",
                     WMI_MAX_WINDOW);
-    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 1)
+    if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 2)
         return fail(WMI_EINVAL, "wmi_bu_search: bad k, estimator or normalize");
     uint64_t na = 0, nb = 0;
     if (int rc = wmi_series_length(st, a, &na))
@@ -358,6 +371,7 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
     prm.estimator = p->estimator;
     prm.tau = p->tau;
     prm.tau_normalize = p->normalize;
+    prm.flags = p->normalize == 2 ? WMI_SUBMIT_ENTROPY : 0u;
     const bool prune = p->p > 0;
     const uint64_t d = p->delta;
 
@@ -374,7 +388,13 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
     std::vector<wmi_window> found;
     std::vector<wmi_query> q;
     std::vector<wmi_result> res;
-    auto threshold = [&](uint64_t m) { return p->normalize ? p->sigma * std::log((double)m) : p->sigma; };
+    std::vector<double> hres;
+    // report threshold of a walker's window: sigma, sigma ln|w| or sigma H(w)
+    auto threshold = [&](const Walker &w) {
+        if (p->normalize == 2)
+            return p->sigma * w.hw;
+        return p->normalize ? p->sigma * std::log((double)(w.we - w.ws)) : p->sigma;
+    };
 
     for (;;) {
         q.clear();
@@ -422,7 +442,7 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     if (w.iw > w.hist[j])
                         w.hist[j] = w.iw;
                     if (w.idle > p->max_idle) {
-                        if (w.iw >= threshold(w.we - w.ws))
+                        if (w.iw >= threshold(w))
                             found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
                         w.cursor = w.we;
                         w.climbing = false;
@@ -452,11 +472,12 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
             break;
         if (q.empty())
             continue;
-        if (int rc = run_queries(st, q, prm, res, stats))
+        if (int rc = run_queries(st, q, prm, res, hres, stats))
             return rc;
         for (Walker &w : walkers) {
             if (w.pend == 1) {
                 w.iw = res[w.req0].mi_base;
+                w.hw = hres.empty() ? 0.0 : hres[3 * w.req0];
                 w.hist.assign(p->history, w.iw);
                 w.idle = 0;
                 w.lrun = w.rrun = 0;
@@ -488,6 +509,8 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     w.ws = w.ring[best].first;
                     w.we = w.ring[best].second;
                     w.iw = ib;
+                    if (!hres.empty())  // a triple's window is its union
+                        w.hw = hres[3 * (w.req0 + best) + ((best == w.left || best == w.right) ? 2 : 0)];
                     w.idle = 0;
                 } else {
                     w.idle++;
@@ -503,7 +526,7 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     stats.noise_skips++;
                 }
                 if (w.idle > p->max_idle) {
-                    if (w.iw >= threshold(w.we - w.ws))
+                    if (w.iw >= threshold(w))
                         found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
                     w.cursor = w.we;
                     w.climbing = false;

@@ -138,6 +138,7 @@ struct wmi_server {
     hipEvent_t ev_origin = nullptr;  // device-time origin of the launch intervals
     std::vector<std::pair<float, float>> intervals;  // launch [start, end) in ms after ev_origin
     int occupancy = 1;
+    Tuning tune;  // the store's work-list choices when the server was created
     std::thread th;
     std::mutex mu;
     std::condition_variable cv;       // request state changes
@@ -253,7 +254,7 @@ int launch(wmi_server *S, Slot &slot, std::deque<Req *> &active, bool &launched)
         d.m = p.r->r.w;
     }
     uint64_t split_pts = 0;
-    const uint32_t n_items = plan_parts(pd, (uint32_t)slot.parts.size(), &split_pts);
+    const uint32_t n_items = plan_parts(pd, (uint32_t)slot.parts.size(), &split_pts, &S->tune);
     if (n_items > S->cap_items || split_pts > S->cap_split)
         return fail(WMI_EINVAL, "server launch exceeds its slot (%u items, %llu points)", n_items,
                     (unsigned long long)split_pts);
@@ -283,6 +284,8 @@ int launch(wmi_server *S, Slot &slot, std::deque<Req *> &active, bool &launched)
     a.k = S->k;
     a.estimator = S->est;
     a.persistent = 1;
+    for (int i = 0; i < 3; ++i)
+        a.strag[i] = S->tune.stragglers[i];
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n_items, (uint64_t)st->cu_count * S->occupancy);
     hipStream_t s = slot.stream;
     HIPCHK(st, hipEventRecord(slot.ev0, s));
@@ -471,6 +474,10 @@ int wmi_server_create(wmi_store *st, const wmi_server_desc *desc, wmi_server **o
     S->arena.init(arena_bytes);
     S->stats.arena_bytes = arena_bytes;
     S->occupancy = main_occupancy(S->k);
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        S->tune = st->tune;
+    }
     S->t0 = std::chrono::steady_clock::now();
     hipError_t e = hipMalloc(&S->arena_dev, arena_bytes);
     if (e == hipSuccess)

@@ -49,6 +49,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 hipError_t launch_clear(const LaunchArgs &a, hipStream_t s);
 hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s);
+hipError_t launch_entropy(const EntropyArgs &a, hipStream_t s);
 hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s);
 hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_parts, Item *queue, WinDesc *win,
@@ -71,6 +72,7 @@ struct wmi_store {
     long long *psi_fix = nullptr;
     int cu_count = 1;
     void *scratch = nullptr;  // device address of this device's no-alloc scratch array
+    wmi::Tuning tune = wmi::default_tuning();  // work-list choices (store mutex)
     std::mutex mu;
     std::condition_variable cv;
     std::vector<wmi::Series> series;

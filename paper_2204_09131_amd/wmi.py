@@ -9,6 +9,7 @@ streams (``Store.add_series`` accepts a CUDA/HIP tensor; ``stream=`` accepts a
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -35,6 +36,7 @@ STORE_STRICT_GRID = 1
 SUBMIT_NONBLOCKING = 1
 SUBMIT_PLAIN = 2
 SUBMIT_NO_REUSE = 4
+SUBMIT_ENTROPY = 8
 MAX_WINDOW = 4096
 MAX_K = 16
 
@@ -48,9 +50,11 @@ WINDOW_RESULT_DTYPE = np.dtype([("mi", "<f8"), ("flags", "<u4"), ("pad", "<u4")]
 WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("mi", "<f8")])
 
 # the symbols include/wmi.h declares
-EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy",
+EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy", "wmi_store_set_tuning",
+           "wmi_store_get_tuning",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
-           "wmi_submit", "wmi_submit_noalloc", "wmi_wait", "wmi_done", "wmi_read", "wmi_batch_replay", "wmi_batch_timing",
+           "wmi_submit", "wmi_submit_noalloc", "wmi_wait", "wmi_done", "wmi_read", "wmi_read_entropy",
+           "wmi_batch_replay", "wmi_batch_timing",
            "wmi_batch_stats_get", "wmi_batch_count_evals", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
            "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
@@ -94,6 +98,22 @@ class _RequestInfo(ctypes.Structure):
     _fields_ = [("windows", ctypes.c_uint64), ("t_arrival_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
                 ("t_first_launch_us", ctypes.c_double), ("t_complete_us", ctypes.c_double),
                 ("state", ctypes.c_int32), ("launches", ctypes.c_uint32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("local_windows", ctypes.c_uint32 * 5), ("triples", ctypes.c_uint32 * 5),
+                ("sweep_windows", ctypes.c_uint32 * 3), ("stragglers", ctypes.c_uint32 * 3)]
+
+
+TUNING_FIELDS = {"local_windows": 5, "triples": 5, "sweep_windows": 3, "stragglers": 3}
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+
+
+def tuning_file(device: int = 0) -> str:
+    """The autotuner's choices for the device's architecture (may not exist)."""
+    import torch
+    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    return os.path.join(TUNING_DIR, f"{arch}.json")
 
 
 class _ServerStats(ctypes.Structure):
@@ -145,6 +165,8 @@ def lib():
         "wmi_last_error": ([], ctypes.c_char_p),
         "wmi_store_create": ([P(_StoreDesc), P(vp)], ctypes.c_int),
         "wmi_store_destroy": ([vp], ctypes.c_int),
+        "wmi_store_set_tuning": ([vp, P(_Tuning)], ctypes.c_int),
+        "wmi_store_get_tuning": ([vp, P(_Tuning)], ctypes.c_int),
         "wmi_series_add": ([vp, vp, u64, P(u32)], ctypes.c_int),
         "wmi_series_add_device": ([vp, vp, u64, vp, P(u32)], ctypes.c_int),
         "wmi_series_remove": ([vp, u32], ctypes.c_int),
@@ -154,6 +176,7 @@ def lib():
         "wmi_wait": ([vp, i64], ctypes.c_int),
         "wmi_done": ([vp], ctypes.c_int),
         "wmi_read": ([vp, vp], ctypes.c_int),
+        "wmi_read_entropy": ([vp, vp], ctypes.c_int),
         "wmi_batch_replay": ([vp, vp, u32], ctypes.c_int),
         "wmi_batch_timing": ([vp, P(_Timing)], ctypes.c_int),
         "wmi_batch_stats_get": ([vp, P(_Stats)], ctypes.c_int),
@@ -235,6 +258,13 @@ class Batch:
         _check(lib().wmi_read(self.h, out.ctypes.data if self.count else None))
         return out
 
+    def read_entropy(self) -> np.ndarray:
+        """Window entropies (count x 3: base, extension, union; NaN where a
+        query has no such window) of a batch submitted with entropy=True."""
+        out = np.zeros((self.count, 3), dtype=np.float64)
+        _check(lib().wmi_read_entropy(self.h, out.ctypes.data if self.count else None))
+        return out
+
     def replay(self, stream=None, direct: bool = False):
         """Enqueue another run (graph launch, or kernel by kernel if direct)."""
         _check(lib().wmi_batch_replay(self.h, _stream_handle(stream), REPLAY_DIRECT if direct else 0))
@@ -275,13 +305,43 @@ class Batch:
 class Store:
     """A set of resident series on one device."""
 
-    def __init__(self, device: int = 0, budget_bytes: int = 0, strict_grid: bool = False):
+    def __init__(self, device: int = 0, budget_bytes: int = 0, strict_grid: bool = False, tuning=None):
+        """tuning: None (the library's defaults), a dict of wmi_tuning fields,
+        or "auto": the autotuner's file for this device's architecture when
+        there is one (tuning_file), else the defaults."""
         d = _StoreDesc(int(device), STORE_STRICT_GRID if strict_grid else 0, int(budget_bytes))
         h = ctypes.c_void_p()
         _check(lib().wmi_store_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
         self.device = device
         self._borrowed = {}
+        if tuning == "auto":
+            path = tuning_file(device)
+            tuning = json.load(open(path))["tuning"] if os.path.exists(path) else None
+        if tuning is not None:
+            self.set_tuning(tuning)
+
+    def set_tuning(self, tuning=None):
+        """Set the work-list choices (dict of wmi_tuning fields; missing
+        fields keep the defaults; None: all defaults)."""
+        if tuning is None:
+            _check(lib().wmi_store_set_tuning(self.h, None))
+            return
+        cur = _Tuning()
+        _check(lib().wmi_store_set_tuning(self.h, None))
+        _check(lib().wmi_store_get_tuning(self.h, ctypes.byref(cur)))
+        for f, n in TUNING_FIELDS.items():
+            if f in tuning:
+                v = list(tuning[f])
+                if len(v) != n:
+                    raise ValueError(f"tuning field {f} needs {n} values")
+                setattr(cur, f, (ctypes.c_uint32 * n)(*[int(x) for x in v]))
+        _check(lib().wmi_store_set_tuning(self.h, ctypes.byref(cur)))
+
+    def get_tuning(self) -> dict:
+        cur = _Tuning()
+        _check(lib().wmi_store_get_tuning(self.h, ctypes.byref(cur)))
+        return {f: list(getattr(cur, f)) for f in TUNING_FIELDS}
 
     def close(self):
         if self.h:
@@ -329,10 +389,10 @@ class Store:
 
     def submit(self, queries, k: int = 4, estimator: int = 0, tau: float = 0.0, tau_normalize: int = 0,
                plain: bool = False, nonblocking: bool = False, no_reuse: bool = False,
-               stream=None) -> Batch:
+               entropy: bool = False, stream=None) -> Batch:
         q = as_queries(queries)
         flags = ((SUBMIT_PLAIN if plain else 0) | (SUBMIT_NONBLOCKING if nonblocking else 0)
-                 | (SUBMIT_NO_REUSE if no_reuse else 0))
+                 | (SUBMIT_NO_REUSE if no_reuse else 0) | (SUBMIT_ENTROPY if entropy else 0))
         p = _params(k, estimator, tau, tau_normalize, flags)
         h = ctypes.c_void_p()
         _check(lib().wmi_submit(self.h, q.ctypes.data if len(q) else None, len(q), ctypes.byref(p),
@@ -371,12 +431,12 @@ class Store:
             b.destroy()
 
     def td_search(self, a: int, b: int, begin: int, end: int, s_max: int, s_min: int, sigma: float,
-                  tau: float = 0.0, p: int = 0, step_div: int = 8, normalize: bool = False, k: int = 4,
+                  tau: float = 0.0, p: int = 0, step_div: int = 8, normalize: int = 0, k: int = 4,
                   estimator: int = 0):
         """Top-down search (wmi_td_search): correlated windows (WINDOW_DTYPE,
         ascending start) and the search counters."""
         prm = _TdParams(int(s_max), int(s_min), int(step_div), int(p), float(sigma), float(tau),
-                        1 if normalize else 0, int(k), int(estimator), 0)
+                        int(normalize), int(k), int(estimator), 0)
         cap = max(1, (int(end) - int(begin)) // max(int(s_min), 1) + 1)
         out = np.zeros(cap, dtype=WINDOW_DTYPE)
         n = ctypes.c_uint64()
@@ -386,12 +446,12 @@ class Store:
         return out[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
 
     def bu_search(self, a: int, b: int, begin: int, end: int, s_min: int, s_max: int, delta: int, sigma: float,
-                  max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: bool = False,
+                  max_idle: int = 2, history: int = 4, tau: float = 0.0, p: int = 0, normalize: int = 0,
                   chunk: int = 0, seed: int = 0, k: int = 4, estimator: int = 0):
         """Bottom-up search (wmi_bu_search): correlated windows (WINDOW_DTYPE,
         ascending start) and the search counters."""
         prm = _BuParams(int(s_min), int(s_max), int(delta), int(max_idle), int(history), int(p), float(sigma),
-                        float(tau), 1 if normalize else 0, int(k), int(estimator), int(chunk),
+                        float(tau), int(normalize), int(k), int(estimator), int(chunk),
                         int(seed) & 0xFFFFFFFFFFFFFFFF, 0, 0)
         cap = max(1, (int(end) - int(begin)) // max(int(s_min), 1) + 1)
         out = np.zeros(cap, dtype=WINDOW_DTYPE)

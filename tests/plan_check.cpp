@@ -19,10 +19,10 @@ static int fail(const char *what, long a, long b)
 }
 
 static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &wq, uint64_t count, bool plain,
-                 bool fuse, const std::vector<uint64_t> &wx, const std::vector<uint64_t> &wy)
+                 bool fuse, const std::vector<uint64_t> &wx, const std::vector<uint64_t> &wy, const Tuning &T)
 {
     Plan P;
-    plan_items(wm, wq, count, plain, P, fuse, &wx, &wy);
+    plan_items(wm, wq, count, plain, P, fuse, &wx, &wy, &T);
     const size_t n = wm.size();
     if (P.items.size() != P.cost.size())
         return fail("cost size", (long)P.items.size(), (long)P.cost.size());
@@ -38,13 +38,14 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
             const uint32_t nw = I.info & 0xFFu;
             if (plain || !fuse)
                 return fail("sweep item without reuse", (long)it, (long)nw);
-            if (nw < 2 || nw > (uint32_t)kSweepWindows || (I.info & 0x0FFFFF00u) || I.win + nw > n)
+            if (nw < 2 || (I.info & 0x0FFFFF00u) || I.win + nw > n || T.sweep_windows[sweep_bucket(wm[I.win])] < 2 ||
+                nw > std::max<uint32_t>(T.sweep_windows[sweep_bucket(wm[I.win])], 3u))
                 return fail("sweep window count", (long)it, (long)nw);
             const uint32_t m = wm[I.win];
             const int64_t dx = (int64_t)(wx[I.win + 1] - wx[I.win]), dy = (int64_t)(wy[I.win + 1] - wy[I.win]);
             const int64_t s = dx / 4;
             if (dx != dy || dx <= 0 || dx % 4 || m < (uint32_t)kSweepMinM || (int64_t)m + s > kSweepRing ||
-                kSweepStrideDiv * s > (int64_t)m)
+                kSweepStrideDiv * s > (int64_t)m || (int64_t)(nw - 1) * s + m > kSweepSpan)
                 return fail("sweep shape", (long)it, (long)s);
             for (uint32_t r = 0; r < nw; ++r) {
                 const uint32_t v = I.win + r;
@@ -65,6 +66,11 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
                 return fail("triple item without fusing", (long)it, (long)nt);
             if (nt < 1 || nt > (uint32_t)kTripleMax || (I.info & 0x1FFFFF00u))
                 return fail("triple count", (long)it, (long)nt);
+            uint32_t umax = 2;
+            for (uint32_t r = 0; r < nt && I.win + 3 * r + 2 < n; ++r)
+                umax = std::max(umax, wm[I.win + 3 * r + 2]);
+            if (nt > T.triples[local_bucket(umax)])
+                return fail("triples above the tuned cap", (long)it, (long)nt);
             for (uint32_t r = 0; r < nt; ++r) {
                 const uint32_t wb = I.win + 3 * r;
                 if (wb + 2 >= n)
@@ -107,6 +113,8 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
             }
             if (slots > (uint32_t)kLocalSlots)
                 return fail("local slots", (long)it, (long)slots);
+            if (!plain && nw > T.local_windows[local_bucket(maxm)])
+                return fail("local windows above the tuned cap", (long)it, (long)nw);
             if (nw * plan_pow2(maxm) > (uint32_t)kLocalSort)
                 return fail("local sort entries", (long)it, (long)(nw * plan_pow2(maxm)));
         } else {
@@ -185,15 +193,19 @@ static int check(const std::vector<uint32_t> &wm, const std::vector<uint32_t> &w
             size_t w0 = w;
             while (w < n && wq[w] == t)
                 ++w;
-            uint32_t slots = 0, maxm = 2, nw = (uint32_t)(w - w0);
-            bool local = true;
-            for (size_t r = w0; r < w; ++r) {
-                local = local && wm[r] <= (uint32_t)kLocalSlots;
+            // it fits when its windows, added one by one to an empty item,
+            // stay within every limit (the cap on windows depends on the
+            // item's largest window so far)
+            uint32_t slots = 0, maxm = 2, nw = 0;
+            bool fits = true;
+            for (size_t r = w0; r < w && fits; ++r) {
+                fits = wm[r] <= (uint32_t)kLocalSlots;
                 slots += (wm[r] + 1u) & ~1u;
                 maxm = std::max(maxm, wm[r]);
+                ++nw;
+                fits = fits && nw <= std::min<uint32_t>(T.local_windows[local_bucket(maxm)], kLocalWindows) &&
+                       slots <= (uint32_t)kLocalSlots && nw * plan_pow2(maxm) <= (uint32_t)kLocalSort;
             }
-            bool fits = local && nw <= (uint32_t)kLocalWindows && slots <= (uint32_t)kLocalSlots &&
-                        nw * plan_pow2(maxm) <= (uint32_t)kLocalSort;
             if (fits)
                 for (size_t r = w0 + 1; r < w; ++r)
                     if (local_item[r] != local_item[w0])
@@ -337,9 +349,18 @@ int main(int argc, char **argv)
                 wy.push_back(rng() & ~3ull);
             }
         }
+        Tuning T = default_tuning();
+        if (c % 2) {  // other work-list choices
+            for (int b = 0; b < 5; ++b) {
+                T.local_windows[b] = 1 + (uint32_t)(rng() % kLocalWindows);
+                T.triples[b] = 1 + (uint32_t)(rng() % kTripleMax);
+            }
+            for (int b = 0; b < 3; ++b)
+                T.sweep_windows[b] = 1 + (uint32_t)(rng() % 40);
+        }
         for (int plain = 0; plain < 2; ++plain)
             for (int fuse = 0; fuse < 2; ++fuse)
-                if (check(wm, wq, count, plain != 0, fuse != 0, wx, wy)) {
+                if (check(wm, wq, count, plain != 0, fuse != 0, wx, wy, T)) {
                     std::printf("case %d style %d plain %d fuse %d\n", c, style, plain, fuse);
                     return 1;
                 }
