@@ -234,6 +234,40 @@ int wmi_submit(wmi_store *store, const wmi_query *host_queries, uint64_t count,
                const wmi_params *params, void *stream, wmi_batch **out);
 
 /*
+ * A run of `count` equally spaced queries of one series pair (the sliding
+ * windows of Definition 3.4, or the shifted windows of Section 6.2 split into
+ * overlap and new part): query i (0 <= i < count) is
+ *     { a, b, start + i * stride, len, ext_len, ext_side }
+ * with the meaning of wmi_query.  40 bytes.
+ */
+typedef struct {
+    uint32_t a, b;
+    uint64_t start;
+    uint32_t count;
+    uint32_t stride;   /* >= 1 when count > 1                                 */
+    uint32_t len;
+    uint32_t ext_len;  /* 0 with ext_side 0: plain windows                    */
+    int32_t ext_side;
+    uint32_t reserved; /* must be 0                                           */
+} wmi_range;
+
+/*
+ * wmi_submit for queries given as runs: the batch holds the queries of
+ * ranges[0], then those of ranges[1], ... (total = sum of count), and gives
+ * bit-identical results to wmi_submit of that list.  The host plans per run,
+ * not per window: the window descriptors, query descriptors and work queue are
+ * written on the device by an expansion kernel at every run of the batch
+ * (submit and each replay), before the estimates, so only the run list
+ * (n_ranges x 40 bytes) crosses PCIe.  A run with count 0 adds nothing.
+ * Every query of a run must be valid as for wmi_submit (it suffices that the
+ * first and the last are).  Flags as wmi_submit except WMI_SUBMIT_PLAIN
+ * (WMI_EINVAL).  Errors as wmi_submit; WMI_EINVAL also for a reserved field
+ * set, stride 0 with count > 1, or more than 2^32 - 16 queries.
+ */
+int wmi_submit_ranges(wmi_store *store, const wmi_range *host_ranges, uint64_t n_ranges,
+                      const wmi_params *params, void *stream, wmi_batch **out);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * evaluation as wmi_submit, without allocating.  Descriptors, sorted

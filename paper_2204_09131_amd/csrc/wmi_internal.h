@@ -205,6 +205,36 @@ struct LaunchArgs {
     uint32_t strag[3];            // straggler thresholds by split_bucket(m)
 };
 
+// A run of equally spaced queries of one series pair, expanded on the device
+// (wmi_submit_ranges).  Query i of the run is at start + i * stride; its
+// windows are win0 + i (plain) or win0 + 3i .. win0 + 3i + 2 (base,
+// extension, union).  kind says how its windows are scheduled; the queue
+// offsets are those the host planner gave the run.
+enum : uint32_t {
+    kRangeLocal = 0,       // plain windows <= kLocalSlots: local items of per_item windows
+    kRangeSweep = 1,       // plain windows: sweep items of per_item windows
+    kRangeSplit = 2,       // plain windows > kLocalSlots: a prep item and split items each
+    kRangeTriple = 3,      // triples with union <= kLocalSlots: triple items of per_item triples
+    kRangeTripleWide = 4,  // other triples: each window alone (local item, or prep + split items)
+};
+
+struct RangeDesc {          // 80 bytes
+    const float *x;         // series a
+    const float *y;         // series b
+    uint64_t start;         // base start of query 0
+    double tau_eff;         // noise threshold of its triples, normalised if requested
+    uint32_t stride, count; // queries
+    uint32_t m, e;          // base points, extension points (0 for plain windows)
+    int32_t side;           // 0 plain, +1 / -1 extension side
+    uint32_t kind, per_item;
+    uint32_t q0, win0;      // first query and window of the run
+    uint32_t item0;         // first local / triple / sweep / split item
+    uint32_t item1;         // kRangeTripleWide: first split item
+    uint32_t prep0;         // first prep item
+    uint32_t sorted0;       // sorted-marginal offset (points) of query 0's first split window
+    uint32_t pad;
+};
+
 // Window entropies (the normalised MI of Section 5.4): per query, H of its
 // windows into hres (3 per query, NaN where a query has no such window; null:
 // extensions only), and with set_tau the noise threshold tau * H(extension)

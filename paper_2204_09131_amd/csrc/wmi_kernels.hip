@@ -58,6 +58,7 @@
 #include <vector>
 
 #include "wmi_internal.h"
+#include "wmi_ranges.h"
 
 namespace wmi {
 
@@ -2492,6 +2493,25 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LaunchArgs a, const Part
     }
 }
 
+// runs of queries: one thread per query writes its window and query
+// descriptors and the queue entries its windows start (expand_query)
+__global__ __launch_bounds__(kBlock) void expand_ranges_kernel(const RangeDesc *rd, uint32_t n_rd, uint32_t n_query,
+                                                               WinDesc *win, QDesc *qd, Item *queue)
+{
+    const uint32_t t = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+    if (t >= n_query)
+        return;
+    uint32_t lo = 0, hi = n_rd - 1u;  // the last run whose first query is at or before t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (rd[mid].q0 <= t)
+            lo = mid;
+        else
+            hi = mid - 1u;
+    }
+    expand_query(rd[lo], t - rd[lo].q0, win, qd, queue);
+}
+
 // plain form: one workgroup per split window, before that window's items
 __global__ __launch_bounds__(kBlock) void prep_kernel(LaunchArgs a)
 {
@@ -2647,6 +2667,16 @@ hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_
     if (n_parts == 0)
         return hipSuccess;
     hipLaunchKernelGGL(expand_kernel, dim3(n_parts), dim3(kBlock), 0, s, a, parts, n_parts, queue, win, qd, cdst);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_ranges(const RangeDesc *rd, uint32_t n_rd, uint32_t n_query, WinDesc *win, QDesc *qd,
+                                Item *queue, hipStream_t s)
+{
+    if (n_rd == 0 || n_query == 0)
+        return hipSuccess;
+    const uint32_t blocks = (n_query + (uint32_t)kBlock - 1u) / (uint32_t)kBlock;
+    hipLaunchKernelGGL(expand_ranges_kernel, dim3(blocks), dim3(kBlock), 0, s, rd, n_rd, n_query, win, qd, queue);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "wmi_internal.h"
+#include "wmi_ranges.h"
 
 namespace wmi {
 
@@ -311,6 +312,121 @@ inline uint32_t plan_parts(PartDesc *pd, uint32_t n, uint64_t *split, const Tuni
         }
     *split = sorted;
     return q;
+}
+
+// Runs of equally spaced queries (wmi_submit_ranges): the kind, the windows
+// or triples per item and the queue offsets of each run, for the device-side
+// expansion (expand_query in wmi_ranges.h).  rd[0..n) come with x, y, start,
+// stride, count (> 0), m, e, side and tau_eff set.  The queue has the layout
+// of plan_queue: prep items (larger windows first), local items (triple and
+// sweep items included) costing at least kTailCost, split items (larger
+// windows first), then the cheaper local items; runs keep their items
+// together.  fuse allows triple and sweep items (off: every window evaluated
+// on its own).  Returns the queue length; *n_win and *split_pts receive the
+// window count and the points of split windows.
+inline uint64_t plan_ranges(RangeDesc *rd, uint32_t n, bool fuse, const Tuning *tune, uint64_t *n_win,
+                            uint64_t *split_pts)
+{
+    const Tuning T = tune ? *tune : default_tuning();
+    std::vector<uint64_t> cost(n, 0), nloc(n, 0), nsplit(n, 0), nprep(n, 0), msplit(n, 0);
+    uint64_t q = 0, w = 0, sp = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        RangeDesc &R = rd[r];
+        R.q0 = (uint32_t)q;
+        R.win0 = (uint32_t)w;
+        R.item0 = R.item1 = R.prep0 = R.sorted0 = 0u;
+        R.per_item = 1u;
+        R.pad = 0u;
+        q += R.count;
+        w += (uint64_t)R.count * (R.side ? 3u : 1u);
+        const uint64_t cnt = R.count;
+        if (R.side == 0) {
+            const uint32_t m = R.m, st = R.stride;
+            if (m > (uint32_t)kLocalSlots) {
+                R.kind = kRangeSplit;
+                const uint64_t ns = (m + kSplitPoints - 1) / kSplitPoints;
+                nprep[r] = cnt;
+                nsplit[r] = cnt * ns;
+                msplit[r] = m;
+                R.sorted0 = (uint32_t)sp;
+                sp += cnt * m;
+            } else if (fuse && cnt >= 2 && st >= 1 && m >= (uint32_t)kSweepMinM && m + st <= (uint32_t)kSweepRing &&
+                       (uint64_t)kSweepStrideDiv * st <= m && T.sweep_windows[sweep_bucket(m)] >= 2) {
+                R.kind = kRangeSweep;
+                const uint32_t C = std::min<uint32_t>(std::min<uint32_t>(T.sweep_windows[sweep_bucket(m)], 255u),
+                                                      ((uint32_t)kSweepSpan - m) / st + 1u);
+                R.per_item = C;
+                nloc[r] = sweep_items(R.count, C);
+                cost[r] = (uint64_t)m * m + (uint64_t)C * m * (16u + 2u * st);
+            } else {
+                R.kind = kRangeLocal;
+                R.per_item = plan_local_per_item(m, &T);
+                nloc[r] = (cnt + R.per_item - 1) / R.per_item;
+                cost[r] = (uint64_t)R.per_item * ((uint64_t)m * m + 4096u);
+            }
+        } else {
+            const uint32_t u = R.m + R.e;
+            if (fuse && u <= (uint32_t)kLocalSlots) {
+                R.kind = kRangeTriple;
+                const uint32_t um = std::max(u, 2u);
+                uint32_t per = std::min<uint32_t>(std::max(T.triples[local_bucket(um)], 1u), kTripleMax);
+                per = std::min(per, (uint32_t)kLocalSlots / ((u + 1u) & ~1u));
+                per = std::max(1u, std::min(per, (uint32_t)kLocalSort / plan_pow2(um)));
+                R.per_item = per;
+                nloc[r] = (cnt + per - 1) / per;
+                cost[r] = (uint64_t)per * ((uint64_t)u * u + 4096u);
+            } else {
+                R.kind = kRangeTripleWide;
+                const uint32_t m3[3] = {R.m, R.e, u};
+                uint64_t L = 0, P = 0, SP = 0, S = 0, mx = 0;
+                for (uint32_t m : m3) {
+                    if (m > (uint32_t)kLocalSlots) {
+                        P++;
+                        SP += m;
+                        S += (m + kSplitPoints - 1) / kSplitPoints;
+                        mx = std::max<uint64_t>(mx, m);
+                    } else {
+                        L++;
+                    }
+                }
+                nloc[r] = cnt * L;
+                nprep[r] = cnt * P;
+                nsplit[r] = cnt * S;
+                msplit[r] = mx;
+                R.sorted0 = (uint32_t)sp;
+                sp += cnt * SP;
+                cost[r] = ~0ull;  // its single-window local items go with the costly ones
+            }
+        }
+    }
+    *n_win = w;
+    *split_pts = sp;
+    auto by = [&](std::vector<uint64_t> key, auto pick) {
+        std::vector<uint32_t> idx;
+        for (uint32_t r = 0; r < n; ++r)
+            if (pick(r))
+                idx.push_back(r);
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return key[a] > key[b]; });
+        return idx;
+    };
+    uint64_t at = 0;
+    for (uint32_t r : by(msplit, [&](uint32_t r) { return nprep[r] > 0; })) {
+        rd[r].prep0 = (uint32_t)at;
+        at += nprep[r];
+    }
+    for (uint32_t r : by(cost, [&](uint32_t r) { return nloc[r] > 0 && cost[r] >= kTailCost; })) {
+        rd[r].item0 = (uint32_t)at;
+        at += nloc[r];
+    }
+    for (uint32_t r : by(msplit, [&](uint32_t r) { return nsplit[r] > 0; })) {
+        (rd[r].kind == kRangeTripleWide ? rd[r].item1 : rd[r].item0) = (uint32_t)at;
+        at += nsplit[r];
+    }
+    for (uint32_t r : by(cost, [&](uint32_t r) { return nloc[r] > 0 && cost[r] < kTailCost; })) {
+        rd[r].item0 = (uint32_t)at;
+        at += nloc[r];
+    }
+    return at;
 }
 
 }  // namespace wmi

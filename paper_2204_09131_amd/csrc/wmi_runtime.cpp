@@ -95,6 +95,13 @@ struct wmi_batch {
     size_t desc_bytes = 0;  // uploaded prefix
     LaunchArgs args{};
     EntropyArgs eargs{};   // the entropy pass, when eargs.n_query > 0
+    // runs of queries (wmi_submit_ranges): expanded into descriptors on the
+    // device at every run
+    const RangeDesc *d_rd = nullptr;
+    uint32_t n_rd = 0;
+    WinDesc *d_win = nullptr;
+    QDesc *d_qd = nullptr;
+    Item *d_queue = nullptr;
     size_t res_bytes = 0;  // downloaded: results, error word, entropies
     uint32_t grid = 0;
     std::vector<uint32_t> win_first_item;  // plain form: first item of each window
@@ -206,6 +213,8 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
     const LaunchArgs &a = b->args;
     if (b->desc_bytes)
         HIPCHK(st, hipMemcpyAsync(b->dev, b->host, b->desc_bytes, hipMemcpyHostToDevice, s));
+    if (b->n_rd)
+        HIPCHK(st, launch_expand_ranges(b->d_rd, b->n_rd, (uint32_t)b->count, b->d_win, b->d_qd, b->d_queue, s));
     HIPCHK(st, launch_clear(a, s));
     if (ev)
         HIPCHK(st, hipEventRecord(ev->p0, s));
@@ -301,7 +310,7 @@ int run_batch(wmi_batch *b, hipStream_t s, int mode)
         return rc;
     }
     b->stats.launches = ((b->params.flags & WMI_SUBMIT_PLAIN) ? 1 + 2ull * b->args.n_win : 3) +
-                        (b->eargs.n_query ? 1 : 0);
+                        (b->eargs.n_query ? 1 : 0) + (b->n_rd ? 1 : 0);
     return WMI_OK;
 }
 
@@ -680,6 +689,8 @@ struct BatchBuild {
     std::vector<uint64_t> wstart;  // windows in query order (a triple: base, extension, union)
     std::vector<uint32_t> wm, wquery, used;
     std::vector<uint64_t> wx, wy;  // address of each window's first x and y value
+    std::vector<RangeDesc> rd;     // runs of queries (wmi_submit_ranges): the descriptor prefix
+    bool ranged = false;
     Tuning tune;
     uint64_t pairs = 0, n_win = 0, n_items = 0, n_prep = 0;
     bool plain = false;
@@ -689,6 +700,8 @@ struct BatchBuild {
            o_qdone = 0, o_counter = 0, o_wmi = 0, o_wflags = 0, o_ready = 0, o_res = 0, o_hres = 0,
            res_bytes = 0, dev_bytes = 0;
 };
+
+void layout_batch(BatchBuild &B, uint64_t count, const wmi_params *p);
 
 int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, BatchBuild &B)
 {
@@ -734,14 +747,24 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
         return fail(WMI_ENOMEM, "wmi_submit: batch too large for one launch (%llu points in large windows)",
                     (unsigned long long)B.plan.split_pts);
 
-    // ---- layout -------------------------------------------------------------
+    layout_batch(B, count, p);
+    return WMI_OK;
+}
+
+// Offsets of the batch's device buffer.  The uploaded prefix [0, desc_bytes)
+// holds the window, item, query and prep-list descriptors, or for runs of
+// queries only the runs (their descriptors are written on the device, right
+// after them).
+void layout_batch(BatchBuild &B, uint64_t count, const wmi_params *p)
+{
     const size_t A = 256;
-    B.o_win = 0;
+    B.o_win = B.ranged ? align_up(B.rd.size() * sizeof(RangeDesc), A) : 0;
     B.o_item = align_up(B.o_win + B.n_win * sizeof(WinDesc), A);
     B.o_qd = align_up(B.o_item + B.n_items * sizeof(Item), A);
     B.o_prep = align_up(B.o_qd + count * sizeof(QDesc), A);
-    B.desc_bytes = align_up(B.o_prep + B.n_prep * sizeof(uint32_t), A);
-    B.o_sorted = B.desc_bytes;
+    const size_t desc_end = align_up(B.o_prep + B.n_prep * sizeof(uint32_t), A);
+    B.desc_bytes = B.ranged ? B.o_win : desc_end;
+    B.o_sorted = desc_end;
     B.o_acc = align_up(B.o_sorted + (size_t)kSortedWords * B.plan.split_pts * sizeof(int32_t), A);
     B.o_wdone = align_up(B.o_acc + B.n_win * sizeof(unsigned long long), A);
     B.o_qdone = align_up(B.o_wdone + B.n_win * sizeof(uint32_t), A);
@@ -757,6 +780,81 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
         B.res_bytes = B.o_hres - B.o_res + 3 * count * sizeof(double);
     }
     B.dev_bytes = align_up(B.o_res + B.res_bytes, A);
+}
+
+// Runs of queries: validated (the first and the last query of each run; the
+// others lie between them), planned per run (plan_ranges) and laid out.
+int build_ranges(wmi_store *st, const wmi_range *rg, uint64_t n_ranges, const wmi_params *p, BatchBuild &B,
+                 uint64_t *count)
+{
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        B.ser = st->series;
+        B.tune = st->tune;
+    }
+    B.ranged = true;
+    uint64_t total = 0;
+    for (uint64_t r = 0; r < n_ranges; ++r) {
+        const wmi_range &g = rg[r];
+        if (g.reserved)
+            return fail(WMI_EINVAL, "range %llu: reserved field must be 0", (unsigned long long)r);
+        if (g.count == 0)
+            continue;
+        if (g.count > 1 && g.stride == 0)
+            return fail(WMI_EINVAL, "range %llu: stride 0 with %u queries", (unsigned long long)r, g.count);
+        const uint64_t span = (uint64_t)(g.count - 1) * g.stride;
+        if (g.start > ~0ull - span)
+            return fail(WMI_EINVAL, "range %llu: start overflows", (unsigned long long)r);
+        wmi_query q{};
+        q.a = g.a;
+        q.b = g.b;
+        q.len = g.len;
+        q.ext_len = g.ext_len;
+        q.ext_side = g.ext_side;
+        const uint64_t ends[2] = {0, span};
+        for (uint64_t i : ends) {
+            q.start = g.start + i;
+            uint64_t s3[3];
+            uint32_t m3[3], nw = 0;
+            if (int rc = query_windows(q, B.ser, total + (i ? g.count - 1 : 0), s3, m3, &nw))
+                return rc;
+        }
+        RangeDesc R{};
+        R.x = B.ser[g.a].d;
+        R.y = B.ser[g.b].d;
+        R.start = g.start;
+        R.stride = g.stride;
+        R.count = g.count;
+        R.m = g.len;
+        R.side = g.ext_side;
+        R.e = g.ext_side ? g.ext_len : 0u;
+        R.tau_eff = p->tau_normalize == 1 ? p->tau * std::log((double)g.ext_len) : p->tau;
+        B.rd.push_back(R);
+        const uint64_t u = (uint64_t)R.m + R.e;
+        B.pairs += (uint64_t)g.count * (R.side ? (uint64_t)R.m * (R.m - 1) + (uint64_t)R.e * (R.e - 1) + u * (u - 1)
+                                               : (uint64_t)R.m * (R.m - 1));
+        B.used.push_back(g.a);
+        B.used.push_back(g.b);
+        total += g.count;
+        if (total > 0xFFFFFFF0ull)
+            return fail(WMI_EINVAL, "wmi_submit_ranges: more than 2^32 - 16 queries");
+    }
+    std::sort(B.used.begin(), B.used.end());
+    B.used.erase(std::unique(B.used.begin(), B.used.end()), B.used.end());
+    if (B.rd.size() > 0xFFFFFFF0ull)
+        return fail(WMI_EINVAL, "wmi_submit_ranges: too many runs");
+    const bool fuse = !(p->flags & WMI_SUBMIT_NO_REUSE);
+    B.n_items = plan_ranges(B.rd.data(), (uint32_t)B.rd.size(), fuse, &B.tune, &B.n_win, &B.plan.split_pts);
+    if (B.n_win > 0x7FFFFFF0ull || B.n_items > 0xFFFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit_ranges: batch too large for one launch (%llu windows)",
+                    (unsigned long long)B.n_win);
+    if (B.plan.split_pts > 0xFFFFFFF0ull)
+        return fail(WMI_ENOMEM, "wmi_submit_ranges: batch too large for one launch (%llu points in large windows)",
+                    (unsigned long long)B.plan.split_pts);
+    B.n_prep = 0;
+    B.plain = false;
+    layout_batch(B, total, p);
+    *count = total;
     return WMI_OK;
 }
 
@@ -850,41 +948,29 @@ void set_entropy_args(const BatchBuild &B, const wmi_params *p, uint64_t count, 
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,
-               wmi_batch **out)
+// A planned batch (query list qs, or runs in B.rd): budget, buffers,
+// descriptors, launch arguments and its first run.
+int start_batch(wmi_store *st, BatchBuild &B, const wmi_query *qs, uint64_t count, const wmi_params *p,
+                void *stream, const char *who, wmi_batch **out)
 {
-    if (!st || !p || !out || (count && !qs))
-        return fail(WMI_EINVAL, "wmi_submit: null argument");
-    *out = nullptr;
-    if (int rc = validate_params(p))
-        return rc;
-    if (count > 0xFFFFFFF0ull)
-        return fail(WMI_EINVAL, "wmi_submit: too many queries in one batch");
-    if (int rc = check_poison(st))
-        return rc;
-    DeviceGuard g(st->device);
-
-    BatchBuild B;
-    if (int rc = build_batch(st, qs, count, p, B))
-        return rc;
     const size_t dev_bytes = B.dev_bytes, desc_bytes = B.desc_bytes;
     if (dev_bytes > st->budget)
-        return fail(WMI_ENOMEM, "wmi_submit: batch needs %zu bytes of device memory, budget is %llu", dev_bytes,
+        return fail(WMI_ENOMEM, "%s: batch needs %zu bytes of device memory, budget is %llu", who, dev_bytes,
                     (unsigned long long)st->budget);
     {
         std::unique_lock<std::mutex> lk(st->mu);
         if (st->inflight + dev_bytes > st->budget) {
             if (p->flags & WMI_SUBMIT_NONBLOCKING)
-                return fail(WMI_EBUSY, "wmi_submit: %zu bytes do not fit beside %llu in flight (budget %llu)",
-                            dev_bytes, (unsigned long long)st->inflight, (unsigned long long)st->budget);
+                return fail(WMI_EBUSY, "%s: %zu bytes do not fit beside %llu in flight (budget %llu)",
+                            who, dev_bytes, (unsigned long long)st->inflight, (unsigned long long)st->budget);
             // running batches release their budget from the stream callback
             st->cv.wait(lk, [&] { return st->inflight + dev_bytes <= st->budget; });
         }
         for (uint32_t id : B.used)
             if (id >= st->series.size() || !st->series[id].live)
-                return fail(WMI_EINVAL, "wmi_submit: series %u removed during submit", id);
+                return fail(WMI_EINVAL, "%s: series %u removed during submit", who, id);
     }
     wmi_batch *b = new wmi_batch();
     b->st = st;
@@ -925,7 +1011,16 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
         return bail(e, "hipEventCreate");
 
     // ---- descriptors and launch arguments ------------------------------------
-    write_descriptors(B, qs, count, p, b->host);
+    if (B.ranged) {
+        std::memcpy(b->host, B.rd.data(), B.rd.size() * sizeof(RangeDesc));
+        b->d_rd = reinterpret_cast<const RangeDesc *>(b->dev);
+        b->n_rd = (uint32_t)B.rd.size();
+        b->d_win = reinterpret_cast<WinDesc *>(b->dev + B.o_win);
+        b->d_qd = reinterpret_cast<QDesc *>(b->dev + B.o_qd);
+        b->d_queue = reinterpret_cast<Item *>(b->dev + B.o_item);
+    } else {
+        write_descriptors(B, qs, count, p, b->host);
+    }
     b->h_res = reinterpret_cast<Result *>(b->host + desc_bytes);
     if (B.plain) {
         b->win_first_item = std::move(B.plan.first_item);
@@ -962,6 +1057,51 @@ int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_par
     }
     *out = b;
     return WMI_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int wmi_submit(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,
+               wmi_batch **out)
+{
+    if (!st || !p || !out || (count && !qs))
+        return fail(WMI_EINVAL, "wmi_submit: null argument");
+    *out = nullptr;
+    if (int rc = validate_params(p))
+        return rc;
+    if (count > 0xFFFFFFF0ull)
+        return fail(WMI_EINVAL, "wmi_submit: too many queries in one batch");
+    if (int rc = check_poison(st))
+        return rc;
+    DeviceGuard g(st->device);
+
+    BatchBuild B;
+    if (int rc = build_batch(st, qs, count, p, B))
+        return rc;
+    return start_batch(st, B, qs, count, p, stream, "wmi_submit", out);
+}
+
+int wmi_submit_ranges(wmi_store *st, const wmi_range *ranges, uint64_t n_ranges, const wmi_params *p, void *stream,
+                      wmi_batch **out)
+{
+    if (!st || !p || !out || (n_ranges && !ranges))
+        return fail(WMI_EINVAL, "wmi_submit_ranges: null argument");
+    *out = nullptr;
+    if (int rc = validate_params(p))
+        return rc;
+    if (p->flags & WMI_SUBMIT_PLAIN)
+        return fail(WMI_EINVAL, "wmi_submit_ranges: no plain form");
+    if (int rc = check_poison(st))
+        return rc;
+    DeviceGuard g(st->device);
+    BatchBuild B;
+    uint64_t count = 0;
+    if (int rc = build_ranges(st, ranges, n_ranges, p, B, &count))
+        return rc;
+    return start_batch(st, B, nullptr, count, p, stream, "wmi_submit_ranges", out);
 }
 
 int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_params *p, void *stream,

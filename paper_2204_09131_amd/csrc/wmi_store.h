@@ -50,6 +50,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 hipError_t launch_clear(const LaunchArgs &a, hipStream_t s);
 hipError_t launch_prep(const LaunchArgs &a, uint32_t n_windows, hipStream_t s);
 hipError_t launch_entropy(const EntropyArgs &a, hipStream_t s);
+hipError_t launch_expand_ranges(const RangeDesc *rd, uint32_t n_rd, uint32_t n_query, WinDesc *win, QDesc *qd,
+                                Item *queue, hipStream_t s);
 hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s);
 hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_parts, Item *queue, WinDesc *win,

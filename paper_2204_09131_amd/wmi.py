@@ -42,6 +42,8 @@ MAX_K = 16
 
 QUERY_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("len", "<u4"),
                         ("ext_len", "<u4"), ("ext_side", "<i4"), ("pad", "<u4")])
+RANGE_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("count", "<u4"), ("stride", "<u4"),
+                        ("len", "<u4"), ("ext_len", "<u4"), ("ext_side", "<i4"), ("pad", "<u4")])
 RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f8"),
                          ("flags", "<u4"), ("pad", "<u4")])
 REQUEST_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("end", "<u8"), ("w", "<u4"),
@@ -53,7 +55,7 @@ WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("m
 EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destroy", "wmi_store_set_tuning",
            "wmi_store_get_tuning",
            "wmi_series_add", "wmi_series_add_device", "wmi_series_remove", "wmi_series_length",
-           "wmi_submit", "wmi_submit_noalloc", "wmi_wait", "wmi_done", "wmi_read", "wmi_read_entropy",
+           "wmi_submit", "wmi_submit_ranges", "wmi_submit_noalloc", "wmi_wait", "wmi_done", "wmi_read", "wmi_read_entropy",
            "wmi_batch_replay", "wmi_batch_timing",
            "wmi_batch_stats_get", "wmi_batch_count_evals", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
@@ -172,6 +174,7 @@ def lib():
         "wmi_series_remove": ([vp, u32], ctypes.c_int),
         "wmi_series_length": ([vp, u32, P(u64)], ctypes.c_int),
         "wmi_submit": ([vp, vp, u64, P(_Params), vp, P(vp)], ctypes.c_int),
+        "wmi_submit_ranges": ([vp, vp, u64, P(_Params), vp, P(vp)], ctypes.c_int),
         "wmi_submit_noalloc": ([vp, vp, u64, P(_Params), vp, vp], ctypes.c_int),
         "wmi_wait": ([vp, i64], ctypes.c_int),
         "wmi_done": ([vp], ctypes.c_int),
@@ -238,6 +241,32 @@ def as_queries(q) -> np.ndarray:
             q = q.view(QUERY_DTYPE) if q.dtype.descr == QUERY_DTYPE.descr else q.astype(QUERY_DTYPE)
         else:
             raise TypeError("queries must be a structured array with the wmi_query layout")
+    return q
+
+
+def make_ranges(a, b, start, count, stride, length, ext_len=0, ext_side=0) -> np.ndarray:
+    """Runs of equally spaced queries (RANGE_DTYPE); scalars broadcast."""
+    start, count, stride = np.broadcast_arrays(np.asarray(start, np.uint64), np.asarray(count, np.uint32),
+                                               np.asarray(stride, np.uint32))
+    a, b, length, ext_len, ext_side = (np.broadcast_to(np.asarray(v), start.shape) for v in
+                                       (a, b, length, ext_len, ext_side))
+    r = np.zeros(start.shape, dtype=RANGE_DTYPE)
+    r["a"], r["b"], r["start"], r["count"], r["stride"] = a, b, start, count, stride
+    r["len"], r["ext_len"], r["ext_side"] = length, ext_len, ext_side
+    return r.reshape(-1)
+
+
+def expand_ranges(ranges) -> np.ndarray:
+    """The query list (QUERY_DTYPE) a run list stands for, in batch order."""
+    r = np.ascontiguousarray(ranges, dtype=RANGE_DTYPE)
+    cnt = r["count"].astype(np.int64)
+    q = np.zeros(int(cnt.sum()), dtype=QUERY_DTYPE)
+    idx = np.repeat(np.arange(len(r)), cnt)
+    pos = np.arange(len(q)) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    for f in ("a", "b", "len", "ext_side"):
+        q[f] = r[f][idx]
+    q["ext_len"] = np.where(r["ext_side"][idx] != 0, r["ext_len"][idx], 0)
+    q["start"] = r["start"][idx] + pos.astype(np.uint64) * r["stride"][idx].astype(np.uint64)
     return q
 
 
@@ -398,6 +427,20 @@ class Store:
         _check(lib().wmi_submit(self.h, q.ctypes.data if len(q) else None, len(q), ctypes.byref(p),
                                 _stream_handle(stream), ctypes.byref(h)))
         return Batch(self, h.value, len(q))
+
+    def submit_ranges(self, ranges, k: int = 4, estimator: int = 0, tau: float = 0.0, tau_normalize: int = 0,
+                      nonblocking: bool = False, no_reuse: bool = False, entropy: bool = False,
+                      stream=None) -> Batch:
+        """wmi_submit_ranges: queries given as runs (RANGE_DTYPE), expanded on
+        the device; results in the order of expand_ranges(ranges)."""
+        r = np.ascontiguousarray(ranges, dtype=RANGE_DTYPE)
+        flags = ((SUBMIT_NONBLOCKING if nonblocking else 0) | (SUBMIT_NO_REUSE if no_reuse else 0)
+                 | (SUBMIT_ENTROPY if entropy else 0))
+        p = _params(k, estimator, tau, tau_normalize, flags)
+        h = ctypes.c_void_p()
+        _check(lib().wmi_submit_ranges(self.h, r.ctypes.data if len(r) else None, len(r), ctypes.byref(p),
+                                       _stream_handle(stream), ctypes.byref(h)))
+        return Batch(self, h.value, int(np.sum(r["count"], dtype=np.uint64)))
 
     def submit_many(self, queries, max_queries: int = 1 << 18, max_points: int = 1 << 26, **kw) -> list:
         """Submit a large query set as consecutive batches, each of at most
