@@ -137,6 +137,10 @@ def sample_pairs(q) -> float:
     return tot + float(np.sum(me * (me - 1)) + np.sum(mu * (mu - 1)))
 
 
+# batches of the headline pass (runs of whole pairs); alternating streams
+HEADLINE_BATCHES = 16
+
+
 def frac(ops, seconds) -> float:
     return ops / seconds / 1e12 / VALU_PEAK_TOPS
 
@@ -146,18 +150,28 @@ def frac(ops, seconds) -> float:
 # ---------------------------------------------------------------------------
 
 def headline(args, wmi, torch, w) -> dict:
-    st = wmi.Store(0, budget_bytes=4 << 30, tuning="auto")
+    st = wmi.Store(0, budget_bytes=8 << 30, tuning="auto")
     ids = [st.add_series(s) for s in w.series]
     assert ids == list(range(len(w.series)))
+    # the query list as runs, one per pair (equally spaced triples): the host
+    # plans per run and the device writes the descriptors at every run
+    q = w.queries
+    n_pairs = len(w.series) * (len(w.series) - 1) // 2
+    cnt = len(q) // n_pairs
+    ab = q[::cnt]
+    rg = wmi.make_ranges(ab["a"], ab["b"], int(q["start"][0]), cnt, int(q["start"][1] - q["start"][0]),
+                         int(q["len"][0]), int(q["ext_len"][0]), int(q["ext_side"][0]))
+    assert np.array_equal(wmi.expand_ranges(rg).view(np.uint8), q.view(np.uint8))
+    groups = np.array_split(rg, HEADLINE_BATCHES)
     t0 = time.perf_counter()
-    batches = st.submit_many(w.queries, k=w.k, tau=w.tau)
+    batches = [st.submit_ranges(g, k=w.k, tau=w.tau) for g in groups]
     first = [b.read() for b in batches]
     t_submit = time.perf_counter() - t0
     for r in first:
         assert np.all(np.isfinite(r["mi_base"])) and np.all(np.isfinite(r["mi_union"]))
-    log(f"headline: {len(batches)} batches, first submit {t_submit:.2f} s")
+    log(f"headline: {len(rg)} runs in {len(batches)} batches, first submit {t_submit:.2f} s")
     # consecutive batches alternate between two streams, so that one batch's
-    # descriptor upload and result download overlap its neighbour's kernel
+    # result download overlaps its neighbour's kernels
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     for _ in range(max(1, args.warmup)):
         for i, b in enumerate(batches):
@@ -177,22 +191,25 @@ def headline(args, wmi, torch, w) -> dict:
     main_ms = float(sum(t["main_ms"] for t in tims))
     for b, r in zip(batches, first):
         assert np.array_equal(b.read().view(np.uint8), r.view(np.uint8)), "replay changed results"
-    evaluated = int(sum(b.count_evals() for b in batches))  # untimed extra pass with counters
+    # untimed extra pass with counters (left out of profiling runs, whose
+    # kernel statistics should hold the timed launches only)
+    evaluated = None if args.no_evals else int(sum(b.count_evals() for b in batches))
     noise = int(sum(np.count_nonzero(r["flags"] & 1) for r in first))
     for b in batches:
         b.destroy()
     st.close()
     pairs = w.ordered_pairs
     launches = len(batches)
-    achieved = OPS_PER_PAIR * evaluated / (main_ms / 1e3) / 1e12
+    achieved = None if evaluated is None else OPS_PER_PAIR * evaluated / (main_ms / 1e3) / 1e12
     log(f"headline: {dt * 1e3:.1f} ms/pass, main kernels {main_ms:.1f} ms, evaluated {evaluated} of {pairs}")
-    return {"dt": dt, "batches": launches, "first_submit_s": t_submit, "main_ms_sum": main_ms,
+    return {"dt": dt, "batches": launches, "runs": int(len(rg)), "first_submit_s": t_submit, "main_ms_sum": main_ms,
             "evaluated": evaluated, "pairs": pairs, "noise_triples": noise,
             "roofline": {"bound": "alu", "kernel": "main_kernel<4>", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                         "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_of(w.name),
+                         "unit": "TOP/s", "frac": None if achieved is None else achieved / VALU_PEAK_TOPS,
+                         "traffic": traffic_of(w.name),
                          "traffic_unit": "HBM bytes per launch (fetch + write, calibrated counters)",
                          "ops_per_distance": OPS_PER_PAIR, "launches_per_step": launches,
-                         "distances_per_launch": evaluated / launches,
+                         "distances_per_launch": None if evaluated is None else evaluated / launches,
                          "ordered_pairs_per_launch": pairs / launches,
                          "avg_launch_ms": main_ms / launches}}
 
@@ -244,6 +261,47 @@ def multiscale(args, wmi, torch, synth) -> dict:
         st.evaluate(q, k=w.k)
         lat.append((time.perf_counter() - s0) * 1e3)
     lat = np.array(lat)
+    # the same windows as runs (one per scale), expanded on the device
+    n = len(w.series[0])
+    rg = np.concatenate([wmi.make_ranges(ids[0], ids[1], 0, (n - wl) // (wl // 8) + 1, wl // 8, wl)
+                         for wl in synth.CFG2_SCALES])
+    assert np.array_equal(wmi.expand_ranges(rg).view(np.uint8), q.view(np.uint8))
+    br = st.submit_ranges(rg, k=w.k)
+    assert np.array_equal(br.read().view(np.uint8), first.view(np.uint8))
+    for _ in range(48):
+        br.replay(direct=True)
+    br.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        br.replay(direct=True)
+    br.wait()
+    torch.cuda.synchronize()
+    r_ms = (time.perf_counter() - t0) / steps * 1e3
+    r_tim = br.timing()
+    br.replay()
+    br.wait()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(steps):
+        br.replay()
+    br.wait()
+    torch.cuda.synchronize()
+    rg_ms = (time.perf_counter() - g0) / steps * 1e3
+    br.destroy()
+    rlat = []
+    for _ in range(args.latency_samples):
+        s0 = time.perf_counter()
+        bb = st.submit_ranges(rg, k=w.k)
+        bb.read()
+        rlat.append((time.perf_counter() - s0) * 1e3)
+        bb.destroy()
+    rlat = np.array(rlat)
+    runs = {"runs": int(len(rg)), "ms_per_step": r_ms, "windows_per_s": n_win / (r_ms / 1e3),
+            "graph_ms_per_step": rg_ms, "graph_windows_per_s": n_win / (rg_ms / 1e3),
+            "device_ms_per_step": r_tim["total_ms"], "main_ms": r_tim["main_ms"],
+            "query_latency_ms": {"p50": float(np.percentile(rlat, 50)), "p99": float(np.percentile(rlat, 99)),
+                                 "samples": int(len(rlat))}}
     plain = None
     if not args.no_plain:
         bp = st.submit(q, k=w.k, plain=True)
@@ -272,6 +330,7 @@ def multiscale(args, wmi, torch, synth) -> dict:
                            "frac_valu_peak": frac(OPS_PER_PAIR * evaluated, main_s)},
            "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                 "samples": int(len(lat)), "what": "fresh submit of the whole batch to results on host"},
+           "as_runs": runs,
            "plain_gpu": plain}
     log(f"multiscale: {out}")
     return out
@@ -283,16 +342,23 @@ def multiscale(args, wmi, torch, synth) -> dict:
 
 def plain_sweep(args, wmi, torch, synth) -> dict:
     """One pair of 4096 points, w = 128, stride 1 (3,969 windows): the
-    incremental form (each window from the one before, Section 7.1.2) and
-    every window on its own, each timed over pipelined direct runs."""
+    incremental form (each window from the one before, Section 7.1.2) with
+    2 .. 16 windows per sweep item, and every window on its own, each timed
+    over pipelined direct runs.  The autotuner's choice for this window size
+    is reported beside them."""
     w = synth.config1()
     out = {"workload": w.name, "windows": len(w.queries), "ordered_pairs": w.ordered_pairs}
-    with wmi.Store(0, tuning="auto") as st:
-        ids = [st.add_series(s) for s in w.series]
-        q = w.queries.copy()
-        q["a"], q["b"] = ids
-        res = {}
-        for name, kw in (("incremental", {}), ("window_by_window", {"no_reuse": True})):
+    with wmi.Store(0, tuning="auto") as st0:
+        tuned = st0.get_tuning()
+    out["autotuned_sweep_windows"] = tuned["sweep_windows"]
+    res = {}
+    variants = [("window_by_window", tuned, {"no_reuse": True})]
+    variants += [(f"incremental_{c}", dict(tuned, sweep_windows=[c, c, c]), {}) for c in (2, 4, 8, 16)]
+    for name, tun, kw in variants:
+        with wmi.Store(0, tuning=tun) as st:
+            ids = [st.add_series(s) for s in w.series]
+            q = w.queries.copy()
+            q["a"], q["b"] = ids
             b = st.submit(q, k=w.k, **kw)
             res[name] = b.read()
             for _ in range(30):
@@ -309,10 +375,13 @@ def plain_sweep(args, wmi, torch, synth) -> dict:
             tim = b.timing()
             ev = b.count_evals()
             b.destroy()
-            out[name] = {"ms_per_step": ms, "windows_per_s": len(q) / (ms / 1e3), "main_kernel_ms": tim["main_ms"],
-                         "distances": int(ev)}
-        assert np.array_equal(res["incremental"].view(np.uint8), res["window_by_window"].view(np.uint8))
-    out["kernel_speedup"] = out["window_by_window"]["main_kernel_ms"] / out["incremental"]["main_kernel_ms"]
+        out[name] = {"ms_per_step": ms, "windows_per_s": len(q) / (ms / 1e3), "main_kernel_ms": tim["main_ms"],
+                     "distances": int(ev)}
+    for name in res:
+        assert np.array_equal(res[name].view(np.uint8), res["window_by_window"].view(np.uint8)), name
+    best = min((n for n, _, _ in variants[1:]), key=lambda n: out[n]["main_kernel_ms"])
+    out["incremental_best"] = best
+    out["kernel_speedup_best"] = out["window_by_window"]["main_kernel_ms"] / out[best]["main_kernel_ms"]
     log(f"plain sweep: {out}")
     return out
 
@@ -449,14 +518,14 @@ def large_search(args, wmi, torch, synth) -> dict:
            "pairs": len(pairs)}
 
     # the dense top-down layers (every window of w = 4096 .. 64 at stride w/8)
-    qd = np.concatenate([synth.make_queries(0, 1, synth.sliding(n, wl, wl // 8), wl) for wl in synth.CFG5_LAYERS])
-    n_win = len(qd)
-    dense_pairs = float(np.sum(qd["len"].astype(np.float64) * (qd["len"] - 1.0)))
+    rd = np.concatenate([wmi.make_ranges(0, 1, 0, (n - wl) // (wl // 8) + 1, wl // 8, wl) for wl in synth.CFG5_LAYERS])
+    n_win = int(rd["count"].sum())
+    dense_pairs = float(np.sum(rd["count"] * rd["len"].astype(np.float64) * (rd["len"] - 1.0)))
     t_sum, main_ms, evaluated = 0.0, 0.0, 0
     for i, (a, b) in enumerate(pairs):
-        q = qd.copy()
-        q["a"], q["b"] = ids[a], ids[b]
-        batches = st.submit_many(q, k=4)
+        r = rd.copy()
+        r["a"], r["b"] = ids[a], ids[b]
+        batches = st.submit_ranges_many(r, k=4)
         for bt in batches:
             bt.wait()
         torch.cuda.synchronize()
@@ -488,7 +557,7 @@ def large_search(args, wmi, torch, synth) -> dict:
     st.bu_search(ids[0], ids[1], 0, 1 << 18, **bu)
     torch.cuda.synchronize()
     for name, fn in (("top_down", lambda a, b: st.td_search(a, b, 0, n, p=2, **td)),
-                     ("bottom_up", lambda a, b: st.bu_search(a, b, 0, n, **bu))):
+                     ("bottom_up_per_pair", lambda a, b: st.bu_search(a, b, 0, n, **bu))):
         agg = {"seconds": 0.0, "windows_found": 0, "windows_evaluated": 0, "ordered_pairs": 0, "batches": 0,
                "noise_skips": 0}
         for a, b in pairs:
@@ -502,6 +571,18 @@ def large_search(args, wmi, torch, synth) -> dict:
         agg["pairs_per_s"] = agg["ordered_pairs"] / agg["seconds"]
         out[name] = agg
         log(f"large {name}: {agg}")
+    # bottom-up over every pair at once: the walkers of all pairs advance
+    # together, one batch per step
+    t0 = time.perf_counter()
+    found, span, stats = st.bu_search_many([(ids[a], ids[b], 0, n) for a, b in pairs], **bu)
+    dt = time.perf_counter() - t0
+    out["bottom_up"] = {"seconds": dt, "windows_found": int(len(found)),
+                        "windows_evaluated": int(stats["windows_evaluated"]),
+                        "ordered_pairs": int(stats["ordered_pairs"]), "batches": int(stats["batches"]),
+                        "noise_skips": int(stats["noise_skips"]),
+                        "windows_per_s": stats["windows_evaluated"] / dt, "pairs_per_s": stats["ordered_pairs"] / dt,
+                        "same_as_per_pair": int(len(found)) == out["bottom_up_per_pair"]["windows_found"]}
+    log(f"large bottom_up (all pairs together): {out['bottom_up']}")
 
     # pruning on one pair: p = 0 against p = 2, graded by overlap accuracy
     runs = {}
@@ -519,7 +600,47 @@ def large_search(args, wmi, torch, synth) -> dict:
     out["isycos_pair0"] = {k: v for k, v in r.items() if k not in ("windows", "stats")}
     out["isycos_pair0"]["windows_found"] = int(len(r["windows"]))
     log(f"large isycos: {out['isycos_pair0']}")
+    out["sigma_tau_estimators"] = sigma_tau_sweep(st, ids, n, wmi)
     st.close()
+    return out
+
+
+def sigma_tau_sweep(st, ids, n, wmi) -> dict:
+    """The thresholds' meaning under the two estimators: Eq. 2 (KSG-2) and
+    Kraskov's first form (KSG-1) on pair 0's first 2^22 points.  The same
+    windows of one layer under both (how their values differ), then the
+    top-down search (normalised thresholds, tau = sigma / 4, p = 2) for
+    several sigma under each, and how far the windows each finds agree."""
+    from scipy.stats import spearmanr
+
+    from paper_2204_09131_amd.search import overlap_accuracy
+    span = min(n, 1 << 22)
+    rr = wmi.make_ranges(ids[0], ids[1], 0, (span - 256) // 32 + 1, 32, 256)
+    vals = {}
+    for est in (0, 1):
+        b = st.submit_ranges(rr, k=4, estimator=est)
+        vals[est] = b.read()["mi_base"]
+        b.destroy()
+    d = vals[1] - vals[0]
+    out = {"span": span, "layer_w256": {"windows": int(len(d)), "mean_ksg2": float(np.mean(vals[0])),
+                                         "mean_ksg1": float(np.mean(vals[1])), "mean_diff": float(np.mean(d)),
+                                         "sd_diff": float(np.std(d)),
+                                         "spearman": float(spearmanr(vals[0], vals[1]).statistic)}}
+    found, rows = {}, []
+    for est in (0, 1):
+        for sg in (0.1, 0.2, 0.3, 0.5):
+            t0 = time.perf_counter()
+            f, stt = st.td_search(ids[0], ids[1], 0, span, s_max=4096, s_min=64, sigma=sg, tau=sg / 4, p=2,
+                                  step_div=8, normalize=1, k=4, estimator=est)
+            found[(est, sg)] = [(int(r["start"]), int(r["len"])) for r in f]
+            rows.append({"estimator": "ksg1" if est else "ksg2", "sigma": sg, "tau": sg / 4, "windows": int(len(f)),
+                         "covered_share": float(np.sum(f["len"].astype(np.int64))) / span,
+                         "noise_skips": int(stt["noise_skips"]), "seconds": time.perf_counter() - t0})
+    out["top_down"] = rows
+    out["agreement"] = [{"sigma": sg, "ksg2_found_by_ksg1": overlap_accuracy(found[(0, sg)], found[(1, sg)]),
+                         "ksg1_found_by_ksg2": overlap_accuracy(found[(1, sg)], found[(0, sg)])}
+                        for sg in (0.1, 0.2, 0.3, 0.5)]
+    log(f"sigma/tau across estimators: {out}")
     return out
 
 
@@ -541,6 +662,8 @@ def main():
                     help="skip the headline workload (profiling runs of the other workloads only)")
     ap.add_argument("--no-large", action="store_true", help="skip the large search")
     ap.add_argument("--large-pairs", type=int, default=0, help="first N of the 28 pairs (0: all)")
+    ap.add_argument("--no-evals", action="store_true",
+                    help="skip the distance-counting pass of the headline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB elementwise kernel (HBM counter calibration)")
     args = ap.parse_args()

@@ -587,6 +587,26 @@ int wmi_bu_search(wmi_store *store, uint32_t a, uint32_t b, uint64_t begin, uint
                   const wmi_bu_params *params, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
                   wmi_search_stats *stats);
 
+/*
+ * wmi_bu_search over several series pairs at once: the walkers of every span
+ * advance together, so each step is one batch over all of them (fewer, larger
+ * batches than one call per span).  Span i gives exactly the windows, in the
+ * same order, that wmi_bu_search(store, a, b, begin, end, params, ...) gives:
+ * chunk numbering (and so the picks) restarts at 0 in every span.  Output:
+ * the windows of span 0 (ascending start), then those of span 1, ...;
+ * host_span[j] (NULL: not written) receives the span of window j.  Capacity
+ * and errors as for wmi_bu_search (sum over spans of (end - begin) / s_min + 1
+ * entries suffice); stats sum over the spans.
+ */
+typedef struct {
+    uint32_t a, b;
+    uint64_t begin, end;
+} wmi_span;
+
+int wmi_bu_search_many(wmi_store *store, const wmi_span *spans, uint64_t n_spans, const wmi_bu_params *params,
+                       wmi_window *host_out, uint32_t *host_span, uint64_t capacity, uint64_t *n_out,
+                       wmi_search_stats *stats);
+
 /* Copy the library's double-precision digamma table psi(1..n) (n <= 8192)
  * to host_out (for checks against an independent construction). */
 int wmi_psi_table(uint32_t n, double *host_out);

@@ -316,6 +316,7 @@ int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params
 }
 
 struct Walker {
+    uint32_t span = 0, a = 0, b = 0;  // the span and series pair it searches
     uint64_t chunk_id = 0;
     uint64_t cursor = 0, cend = 0;  // unexplored rest of the chunk
     uint64_t picks = 0;
@@ -345,27 +346,44 @@ wmi_query window_query(uint32_t a, uint32_t b, uint64_t s, uint64_t e)
 
 }  // namespace
 
-extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
-                             const wmi_bu_params *p, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
-                             wmi_search_stats *stats_out)
+namespace {
+
+// The walkers of every span, advanced together (one batch per step).
+int bu_search(wmi_store *st, const wmi_span *spans, uint64_t n_spans, const wmi_bu_params *p, wmi_window *host_out,
+              uint32_t *host_span, uint64_t capacity, uint64_t *n_out, wmi_search_stats *stats_out, const char *who)
 {
     const auto t0 = std::chrono::steady_clock::now();
-    if (!st || !p || !n_out)
-        return fail(WMI_EINVAL, "wmi_bu_search: null argument");
+    if (!st || !p || !n_out || (n_spans && !spans))
+        return fail(WMI_EINVAL, "%s: null argument", who);
     *n_out = 0;
     if (p->s_min < 2 || p->s_min > p->s_max || p->s_max > (uint32_t)WMI_MAX_WINDOW || p->delta < 1 ||
         p->history < 1 || p->flags || p->reserved)
-        return fail(WMI_EINVAL, "wmi_bu_search: need 2 <= s_min <= s_max <= %d, delta >= 1, history >= 1",
+        return fail(WMI_EINVAL, "%s: need 2 <= s_min <= s_max <= %d, delta >= 1, history >= 1", who,
                     WMI_MAX_WINDOW);
     if (p->k < 1 || p->k > WMI_MAX_K || p->estimator > 1 || p->normalize > 2)
-        return fail(WMI_EINVAL, "wmi_bu_search: bad k, estimator or normalize");
-    uint64_t na = 0, nb = 0;
-    if (int rc = wmi_series_length(st, a, &na))
-        return rc;
-    if (int rc = wmi_series_length(st, b, &nb))
-        return rc;
-    if (begin > end || end > std::min(na, nb))
-        return fail(WMI_EINVAL, "wmi_bu_search: range outside the series");
+        return fail(WMI_EINVAL, "%s: bad k, estimator or normalize", who);
+    std::vector<Walker> walkers;
+    for (uint64_t si = 0; si < n_spans; ++si) {
+        const wmi_span &sp = spans[si];
+        uint64_t na = 0, nb = 0;
+        if (int rc = wmi_series_length(st, sp.a, &na))
+            return rc;
+        if (int rc = wmi_series_length(st, sp.b, &nb))
+            return rc;
+        if (sp.begin > sp.end || sp.end > std::min(na, nb))
+            return fail(WMI_EINVAL, "%s: span %llu outside the series", who, (unsigned long long)si);
+        const uint64_t chunk = p->chunk ? p->chunk : std::max<uint64_t>(sp.end - sp.begin, 1);
+        for (uint64_t c0 = sp.begin, id = 0; c0 < sp.end; c0 += chunk, ++id) {
+            Walker w;
+            w.span = (uint32_t)si;
+            w.a = sp.a;
+            w.b = sp.b;
+            w.chunk_id = id;
+            w.cursor = c0;
+            w.cend = std::min(sp.end, c0 + chunk);
+            walkers.push_back(w);
+        }
+    }
     wmi_params prm{};
     prm.k = p->k;
     prm.estimator = p->estimator;
@@ -375,17 +393,9 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
     const bool prune = p->p > 0;
     const uint64_t d = p->delta;
 
-    std::vector<Walker> walkers;
-    const uint64_t chunk = p->chunk ? p->chunk : std::max<uint64_t>(end - begin, 1);
-    for (uint64_t c0 = begin, id = 0; c0 < end; c0 += chunk, ++id) {
-        Walker w;
-        w.chunk_id = id;
-        w.cursor = c0;
-        w.cend = std::min(end, c0 + chunk);
-        walkers.push_back(w);
-    }
     wmi_search_stats stats{};
     std::vector<wmi_window> found;
+    std::vector<uint32_t> found_span;
     std::vector<wmi_query> q;
     std::vector<wmi_result> res;
     std::vector<double> hres;
@@ -411,7 +421,7 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     w.we = w.cursor + p->s_min;
                     w.pend = 1;
                     w.req0 = q.size();
-                    q.push_back(window_query(a, b, w.ws, w.we));
+                    q.push_back(window_query(w.a, w.b, w.ws, w.we));
                     stats.windows_visited++;
                     break;
                 }
@@ -442,8 +452,10 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     if (w.iw > w.hist[j])
                         w.hist[j] = w.iw;
                     if (w.idle > p->max_idle) {
-                        if (w.iw >= threshold(w))
+                        if (w.iw >= threshold(w)) {
                             found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
+                            found_span.push_back(w.span);
+                        }
                         w.cursor = w.we;
                         w.climbing = false;
                     }
@@ -452,13 +464,13 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                 w.pend = 2;
                 w.req0 = q.size();
                 for (size_t i = 0; i < w.ring.size(); ++i) {
-                    wmi_query x = window_query(a, b, w.ring[i].first, w.ring[i].second);
+                    wmi_query x = window_query(w.a, w.b, w.ring[i].first, w.ring[i].second);
                     if ((int)i == w.left) {  // base w, extension on the left
-                        x = window_query(a, b, w.ws, w.we);
+                        x = window_query(w.a, w.b, w.ws, w.we);
                         x.ext_len = (uint32_t)rd;
                         x.ext_side = -1;
                     } else if ((int)i == w.right) {
-                        x = window_query(a, b, w.ws, w.we);
+                        x = window_query(w.a, w.b, w.ws, w.we);
                         x.ext_len = (uint32_t)rd;
                         x.ext_side = 1;
                     }
@@ -526,27 +538,54 @@ extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t beg
                     stats.noise_skips++;
                 }
                 if (w.idle > p->max_idle) {
-                    if (w.iw >= threshold(w))
+                    if (w.iw >= threshold(w)) {
                         found.push_back(wmi_window{w.ws, (uint32_t)(w.we - w.ws), 0, w.iw});
+                        found_span.push_back(w.span);
+                    }
                     w.cursor = w.we;
                     w.climbing = false;
                 }
             }
         }
     }
-    std::sort(found.begin(), found.end(),
-              [](const wmi_window &x, const wmi_window &y) { return x.start < y.start; });
+    // by span, then start
+    std::vector<size_t> order(found.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return found_span[x] != found_span[y] ? found_span[x] < found_span[y] : found[x].start < found[y].start;
+    });
     *n_out = found.size();
     if (found.size() > capacity)
-        return fail(WMI_EINVAL, "wmi_bu_search: %llu windows found, room for %llu", (unsigned long long)found.size(),
+        return fail(WMI_EINVAL, "%s: %llu windows found, room for %llu", who, (unsigned long long)found.size(),
                     (unsigned long long)capacity);
     if (!found.empty() && !host_out)
-        return fail(WMI_EINVAL, "wmi_bu_search: null output");
-    if (!found.empty())
-        std::memcpy(host_out, found.data(), found.size() * sizeof(wmi_window));
+        return fail(WMI_EINVAL, "%s: null output", who);
+    for (size_t i = 0; i < order.size(); ++i) {
+        host_out[i] = found[order[i]];
+        if (host_span)
+            host_span[i] = found_span[order[i]];
+    }
     stats.layers = 1;
     stats.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats_out)
         *stats_out = stats;
     return WMI_OK;
+}
+
+}  // namespace
+
+extern "C" int wmi_bu_search(wmi_store *st, uint32_t a, uint32_t b, uint64_t begin, uint64_t end,
+                             const wmi_bu_params *p, wmi_window *host_out, uint64_t capacity, uint64_t *n_out,
+                             wmi_search_stats *stats_out)
+{
+    const wmi_span sp{a, b, begin, end};
+    return bu_search(st, &sp, 1, p, host_out, nullptr, capacity, n_out, stats_out, "wmi_bu_search");
+}
+
+extern "C" int wmi_bu_search_many(wmi_store *st, const wmi_span *spans, uint64_t n_spans, const wmi_bu_params *p,
+                                  wmi_window *host_out, uint32_t *host_span, uint64_t capacity, uint64_t *n_out,
+                                  wmi_search_stats *stats_out)
+{
+    return bu_search(st, spans, n_spans, p, host_out, host_span, capacity, n_out, stats_out, "wmi_bu_search_many");
 }

@@ -49,6 +49,7 @@ RESULT_DTYPE = np.dtype([("mi_base", "<f8"), ("mi_ext", "<f8"), ("mi_union", "<f
 REQUEST_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("start", "<u8"), ("end", "<u8"), ("w", "<u4"),
                           ("stride", "<u4")])
 WINDOW_RESULT_DTYPE = np.dtype([("mi", "<f8"), ("flags", "<u4"), ("pad", "<u4")])
+SPAN_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("begin", "<u8"), ("end", "<u8")])
 WINDOW_DTYPE = np.dtype([("start", "<u8"), ("len", "<u4"), ("layer", "<u4"), ("mi", "<f8")])
 
 # the symbols include/wmi.h declares
@@ -60,7 +61,7 @@ EXPORTS = ("wmi_version", "wmi_last_error", "wmi_store_create", "wmi_store_destr
            "wmi_batch_stats_get", "wmi_batch_count_evals", "wmi_batch_destroy", "wmi_debug_window", "wmi_psi_table",
            "wmi_server_create", "wmi_server_submit", "wmi_server_wait", "wmi_server_info",
            "wmi_server_read", "wmi_server_stats_get", "wmi_server_clock_us", "wmi_server_destroy",
-           "wmi_td_search", "wmi_bu_search")
+           "wmi_td_search", "wmi_bu_search", "wmi_bu_search_many")
 REPLAY_DIRECT = 1
 
 
@@ -197,6 +198,7 @@ def lib():
         "wmi_server_destroy": ([vp], ctypes.c_int),
         "wmi_td_search": ([vp, u32, u32, u64, u64, P(_TdParams), vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
         "wmi_bu_search": ([vp, u32, u32, u64, u64, P(_BuParams), vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
+        "wmi_bu_search_many": ([vp, vp, u64, P(_BuParams), vp, vp, u64, P(u64), P(_SearchStats)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -245,14 +247,11 @@ def as_queries(q) -> np.ndarray:
 
 
 def make_ranges(a, b, start, count, stride, length, ext_len=0, ext_side=0) -> np.ndarray:
-    """Runs of equally spaced queries (RANGE_DTYPE); scalars broadcast."""
-    start, count, stride = np.broadcast_arrays(np.asarray(start, np.uint64), np.asarray(count, np.uint32),
-                                               np.asarray(stride, np.uint32))
-    a, b, length, ext_len, ext_side = (np.broadcast_to(np.asarray(v), start.shape) for v in
-                                       (a, b, length, ext_len, ext_side))
-    r = np.zeros(start.shape, dtype=RANGE_DTYPE)
-    r["a"], r["b"], r["start"], r["count"], r["stride"] = a, b, start, count, stride
-    r["len"], r["ext_len"], r["ext_side"] = length, ext_len, ext_side
+    """Runs of equally spaced queries (RANGE_DTYPE); arguments broadcast."""
+    cols = np.broadcast_arrays(*(np.asarray(v) for v in (a, b, start, count, stride, length, ext_len, ext_side)))
+    r = np.zeros(cols[0].shape, dtype=RANGE_DTYPE)
+    for f, v in zip(("a", "b", "start", "count", "stride", "len", "ext_len", "ext_side"), cols):
+        r[f] = v
     return r.reshape(-1)
 
 
@@ -442,6 +441,37 @@ class Store:
                                        _stream_handle(stream), ctypes.byref(h)))
         return Batch(self, h.value, int(np.sum(r["count"], dtype=np.uint64)))
 
+    def submit_ranges_many(self, ranges, max_queries: int = 1 << 20, max_points: int = 1 << 26, **kw) -> list:
+        """Submit runs as consecutive batches of at most max_queries queries
+        and (once a batch holds one) max_points window points, cutting runs
+        where needed; results concatenate to those of expand_ranges(ranges)."""
+        r = np.ascontiguousarray(ranges, dtype=RANGE_DTYPE)
+        per = (r["len"].astype(np.int64) +
+               np.where(r["ext_side"] != 0, r["len"].astype(np.int64) + 2 * r["ext_len"].astype(np.int64), 0))
+        out, cur, cq, cp = [], [], 0, 0
+        for i in range(len(r)):
+            left, start = int(r["count"][i]), int(r["start"][i])
+            while left > 0:
+                room = min(max_queries - cq, max(0 if cq else 1, (max_points - cp) // max(int(per[i]), 1)))
+                take = min(left, room)
+                if take <= 0:
+                    out.append(self.submit_ranges(np.array(cur, dtype=RANGE_DTYPE), **kw))
+                    cur, cq, cp = [], 0, 0
+                    continue
+                g = r[i].copy()
+                g["start"], g["count"] = start, take
+                cur.append(g)
+                cq += take
+                cp += take * int(per[i])
+                start += take * int(r["stride"][i])
+                left -= take
+                if cq >= max_queries or cp >= max_points:
+                    out.append(self.submit_ranges(np.array(cur, dtype=RANGE_DTYPE), **kw))
+                    cur, cq, cp = [], 0, 0
+        if cur:
+            out.append(self.submit_ranges(np.array(cur, dtype=RANGE_DTYPE), **kw))
+        return out
+
     def submit_many(self, queries, max_queries: int = 1 << 18, max_points: int = 1 << 26, **kw) -> list:
         """Submit a large query set as consecutive batches, each of at most
         max_queries queries and (once it holds one) max_points window points;
@@ -503,6 +533,27 @@ class Store:
         _check(lib().wmi_bu_search(self.h, int(a), int(b), int(begin), int(end), ctypes.byref(prm),
                                    out.ctypes.data, cap, ctypes.byref(n), ctypes.byref(st)))
         return out[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
+
+    def bu_search_many(self, spans, s_min: int, s_max: int, delta: int, sigma: float, max_idle: int = 2,
+                       history: int = 4, tau: float = 0.0, p: int = 0, normalize: int = 0, chunk: int = 0,
+                       seed: int = 0, k: int = 4, estimator: int = 0):
+        """wmi_bu_search_many over spans [(a, b, begin, end), ...]: the
+        correlated windows (WINDOW_DTYPE, by span then start), the span of
+        each, and the search counters summed over the spans."""
+        sp = np.zeros(len(spans), dtype=SPAN_DTYPE)
+        for i, (a, b, begin, end) in enumerate(spans):
+            sp[i] = (a, b, begin, end)
+        prm = _BuParams(int(s_min), int(s_max), int(delta), int(max_idle), int(history), int(p), float(sigma),
+                        float(tau), int(normalize), int(k), int(estimator), int(chunk),
+                        int(seed) & 0xFFFFFFFFFFFFFFFF, 0, 0)
+        cap = max(1, int(np.sum((sp["end"].astype(np.int64) - sp["begin"].astype(np.int64)) // max(int(s_min), 1) + 1)))
+        out = np.zeros(cap, dtype=WINDOW_DTYPE)
+        span = np.zeros(cap, dtype=np.uint32)
+        n = ctypes.c_uint64()
+        st = _SearchStats()
+        _check(lib().wmi_bu_search_many(self.h, sp.ctypes.data if len(sp) else None, len(sp), ctypes.byref(prm),
+                                        out.ctypes.data, span.ctypes.data, cap, ctypes.byref(n), ctypes.byref(st)))
+        return out[:n.value].copy(), span[:n.value].copy(), {f: getattr(st, f) for f, _ in _SearchStats._fields_}
 
     def debug_window(self, a: int, b: int, start: int, length: int, k: int = 4, estimator: int = 0) -> dict:
         q = np.zeros(1, dtype=QUERY_DTYPE)

@@ -145,3 +145,26 @@ def test_isycos_selection_runs_the_selected_search(wmi):
     assert np.array_equal(ref, r["windows"])
     assert (r["nscore_td"] > r["nscore_bu"]) == (r["selected"] == "top-down")
     st.close()
+
+
+def test_bu_many_spans_match_single_calls(wmi):
+    """Walkers of several spans in one batch per step: every span gives the
+    windows (and bit-identical estimates) of its own call."""
+    series = [synth.cfg2_pair(6000, 41)[0], synth.cfg2_pair(6000, 41)[1], synth.cfg2_pair(6000, 42)[1]]
+    spans = [(0, 1, 0, 6000), (1, 2, 500, 5500), (0, 2, 0, 4000), (0, 1, 3000, 6000), (2, 0, 100, 100)]
+    kw = dict(s_min=48, s_max=384, delta=24, sigma=0.15, max_idle=1, history=3, tau=0.04, p=1, normalize=1,
+              chunk=1500, seed=9)
+    with wmi.Store(0) as st:
+        assert [st.add_series(s) for s in series] == [0, 1, 2]
+        got, span, stats = st.bu_search_many(spans, **kw)
+        ref, tot = [], 0
+        for i, (a, b, s0, e0) in enumerate(spans):
+            r, s1 = st.bu_search(a, b, s0, e0, **kw)
+            ref.append(r)
+            tot += s1["windows_evaluated"]
+    for i, r in enumerate(ref):
+        mine = got[span == i]
+        assert np.array_equal(mine.view(np.uint8), r.view(np.uint8)), i
+    assert np.all(np.diff(span.astype(np.int64)) >= 0)
+    assert stats["windows_evaluated"] == tot
+    log(f"bu many: {len(got)} windows over {len(spans)} spans in {stats['batches']} batches")
