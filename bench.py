@@ -57,7 +57,16 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # traffic (256 MiB read, 256 MiB written).  Valid only for the kernel source
 # it was taken on (hash of the kernel and descriptor sources); keyed by
 # workload name.
-TRAFFIC = {}
+TRAFFIC = {
+    "cfg3_allpairs_64x32768_w256_s8_triples": {
+        "fetch_bytes": 314485424, "write_bytes": 1528980723,
+        "kernel_sha256": "176cad1055a20ee395d776c36b16d8e5ce0daea8a414d3c0aebc55454964a431",
+        "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
+    "cfg2_multiscale_n65536_w32-4096_s8th": {
+        "fetch_bytes": 105265834, "write_bytes": 83407704,
+        "kernel_sha256": "176cad1055a20ee395d776c36b16d8e5ce0daea8a414d3c0aebc55454964a431",
+        "source": "profiles/main_kernel_cfg2_multiscale.md"},
+}
 
 
 def kernel_source_hash() -> str:
@@ -559,7 +568,7 @@ def large_search(args, wmi, torch, synth) -> dict:
     for name, fn in (("top_down", lambda a, b: st.td_search(a, b, 0, n, p=2, **td)),
                      ("bottom_up_per_pair", lambda a, b: st.bu_search(a, b, 0, n, **bu))):
         agg = {"seconds": 0.0, "windows_found": 0, "windows_evaluated": 0, "ordered_pairs": 0, "batches": 0,
-               "noise_skips": 0}
+               "noise_skips": 0, "submit_s": 0.0, "wait_s": 0.0}
         for a, b in pairs:
             t0 = time.perf_counter()
             found, stats = fn(ids[a], ids[b])
@@ -567,6 +576,8 @@ def large_search(args, wmi, torch, synth) -> dict:
             agg["windows_found"] += int(len(found))
             for f in ("windows_evaluated", "ordered_pairs", "batches", "noise_skips"):
                 agg[f] += int(stats[f])
+            agg["submit_s"] += stats["submit_ms"] / 1e3
+            agg["wait_s"] += stats["wait_ms"] / 1e3
         agg["windows_per_s"] = agg["windows_evaluated"] / agg["seconds"]
         agg["pairs_per_s"] = agg["ordered_pairs"] / agg["seconds"]
         out[name] = agg
@@ -580,6 +591,7 @@ def large_search(args, wmi, torch, synth) -> dict:
                         "windows_evaluated": int(stats["windows_evaluated"]),
                         "ordered_pairs": int(stats["ordered_pairs"]), "batches": int(stats["batches"]),
                         "noise_skips": int(stats["noise_skips"]),
+                        "submit_s": stats["submit_ms"] / 1e3, "wait_s": stats["wait_ms"] / 1e3,
                         "windows_per_s": stats["windows_evaluated"] / dt, "pairs_per_s": stats["ordered_pairs"] / dt,
                         "same_as_per_pair": int(len(found)) == out["bottom_up_per_pair"]["windows_found"]}
     log(f"large bottom_up (all pairs together): {out['bottom_up']}")

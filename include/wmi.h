@@ -488,6 +488,9 @@ typedef struct {
     uint64_t noise_skips;        /* shifts cancelled after p detections in a row  */
     uint64_t batches;            /* batches submitted                             */
     double wall_ms;              /* whole call                                    */
+    double submit_ms;            /* of which inside batch submission (planning,
+                                    upload, launch)                              */
+    double wait_ms;              /* of which waiting for and reading results      */
 } wmi_search_stats;
 
 /*

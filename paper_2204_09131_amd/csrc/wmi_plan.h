@@ -31,12 +31,10 @@ struct Plan {
     uint64_t split_pts = 0;
 };
 
+// The power of two at or above v (1 for v <= 1).
 inline uint32_t plan_pow2(uint32_t v)
 {
-    uint32_t P = 1;
-    while (P < v)
-        P <<= 1;
-    return P;
+    return v <= 1u ? 1u : 1u << (32 - __builtin_clz(v - 1u));
 }
 
 // wm[w]: points of window w; wquery[w]: its query (non-decreasing, every query
@@ -164,7 +162,7 @@ inline void plan_items(const std::vector<uint32_t> &wm, const std::vector<uint32
             continue;
         }
         close_tri();
-        if (!plain) {
+        if (!plain && nw > 1) {
             // start a fresh item rather than cut a query that fits in one
             bool all_local = true, whole = true;
             Cur sim;

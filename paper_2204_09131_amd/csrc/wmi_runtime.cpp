@@ -710,9 +710,15 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
         B.ser = st->series;
         B.tune = st->tune;
     }
-    B.wstart.reserve(count);
-    B.wm.reserve(count);
-    B.wquery.reserve(count);
+    uint64_t nw_all = 0;
+    for (uint64_t t = 0; t < count; ++t)
+        nw_all += qs[t].ext_side ? 3u : 1u;
+    B.wstart.reserve(nw_all);
+    B.wm.reserve(nw_all);
+    B.wquery.reserve(nw_all);
+    B.wx.reserve(nw_all);
+    B.wy.reserve(nw_all);
+    B.used.reserve(2 * count);
     for (uint64_t t = 0; t < count; ++t) {
         uint64_t s3[3];
         uint32_t m3[3], nw = 0;

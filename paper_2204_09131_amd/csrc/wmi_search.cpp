@@ -38,6 +38,9 @@ uint64_t triple_pairs(uint64_t m, uint64_t e)
     return u <= (uint64_t)kLocalSlots ? window_pairs(u) : window_pairs(m) + window_pairs(e) + window_pairs(u);
 }
 
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
+
 struct Eval {
     double mi = 0.0;   // I(w)
     double h = 0.0;    // H(w) when the batch computed entropies
@@ -45,33 +48,45 @@ struct Eval {
 };
 
 // Evaluate windows of s_w points at the given starts (as noise triples with a
-// delta-point right extension when triple is set) in chunked batches.
+// delta-point right extension when triple is set) in chunked batches.  The
+// starts of a partition's grid advance by delta: each such stretch goes to
+// the device as one run (wmi_submit_ranges), whose descriptors the device
+// writes.
 int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> &starts, uint32_t s_w,
              uint32_t delta, bool triple, const wmi_params &prm, std::vector<Eval> &out, wmi_search_stats &stats)
 {
     out.assign(starts.size(), Eval());
     const uint64_t per_q = triple ? 2ull * s_w : s_w;
     const uint64_t chunk = std::max<uint64_t>(1, std::min(kChunkQueries, kChunkPoints / per_q));
-    std::vector<wmi_query> q;
+    std::vector<wmi_range> q;
     std::vector<wmi_result> r;
     std::vector<double> h;
     const bool ent = (prm.flags & WMI_SUBMIT_ENTROPY) != 0;
     for (uint64_t i0 = 0; i0 < starts.size(); i0 += chunk) {
         const uint64_t n = std::min<uint64_t>(chunk, starts.size() - i0);
-        q.assign(n, wmi_query());
-        for (uint64_t i = 0; i < n; ++i) {
-            wmi_query &x = q[i];
+        q.clear();
+        for (uint64_t i = 0; i < n;) {
+            uint64_t j = i + 1;
+            while (j < n && starts[i0 + j] == starts[i0 + j - 1] + delta)
+                ++j;
+            wmi_range x{};
             x.a = a;
             x.b = b;
             x.start = starts[i0 + i];
+            x.count = (uint32_t)(j - i);
+            x.stride = delta;
             x.len = triple ? s_w - delta : s_w;
             x.ext_len = triple ? delta : 0;
             x.ext_side = triple ? 1 : 0;
-            x.reserved = 0;
+            q.push_back(x);
+            i = j;
         }
         wmi_batch *bt = nullptr;
-        if (int rc = wmi_submit(st, q.data(), n, &prm, nullptr, &bt))
+        auto t0 = Clock::now();
+        if (int rc = wmi_submit_ranges(st, q.data(), q.size(), &prm, nullptr, &bt))
             return rc;
+        stats.submit_ms += ms_since(t0);
+        t0 = Clock::now();
         r.assign(n, wmi_result());
         int rc = wmi_read(bt, r.data());
         if (rc == WMI_OK && ent) {
@@ -79,6 +94,7 @@ int evaluate(wmi_store *st, uint32_t a, uint32_t b, const std::vector<uint64_t> 
             rc = wmi_read_entropy(bt, h.data());
         }
         (void)wmi_batch_destroy(bt);
+        stats.wait_ms += ms_since(t0);
         if (rc)
             return rc;
         for (uint64_t i = 0; i < n; ++i) {
@@ -291,12 +307,16 @@ int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params
             ++i1;
         }
         wmi_batch *bt = nullptr;
+        auto t0 = Clock::now();
         if (int rc = wmi_submit(st, q.data() + i0, i1 - i0, &prm, nullptr, &bt))
             return rc;
+        stats.submit_ms += ms_since(t0);
+        t0 = Clock::now();
         int rc = wmi_read(bt, r.data() + i0);
         if (rc == WMI_OK && ent)
             rc = wmi_read_entropy(bt, h.data() + 3 * i0);
         (void)wmi_batch_destroy(bt);
+        stats.wait_ms += ms_since(t0);
         if (rc)
             return rc;
         stats.batches++;

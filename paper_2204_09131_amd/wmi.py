@@ -146,7 +146,8 @@ class _SearchStats(ctypes.Structure):
     _fields_ = [("layers", ctypes.c_uint64), ("windows_visited", ctypes.c_uint64),
                 ("windows_evaluated", ctypes.c_uint64), ("ordered_pairs", ctypes.c_uint64),
                 ("noise_detections", ctypes.c_uint64), ("noise_skips", ctypes.c_uint64),
-                ("batches", ctypes.c_uint64), ("wall_ms", ctypes.c_double)]
+                ("batches", ctypes.c_uint64), ("wall_ms", ctypes.c_double), ("submit_ms", ctypes.c_double),
+                ("wait_ms", ctypes.c_double)]
 
 
 _lib = None
