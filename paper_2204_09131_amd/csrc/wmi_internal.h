@@ -97,6 +97,7 @@ constexpr uint32_t kWaitLimit = 1u << 22;    // polls before a dependency wait g
 // device (descriptors, sorted data, counters, estimates of one call).
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 constexpr uint32_t kErrWait = 1u;            // error word: a dependency wait gave up
+constexpr uint32_t kErrItemKind = 2u;        // error word: an item the kernel variant does not run
 // ready word of a split window, written by its prep item once the sorted data
 // is in HBM: kReady, kReadyOffGrid if a value is off the grid, and the key
 // index bits nb (0: 64-bit keys) from kReadyNbShift
@@ -203,6 +204,9 @@ struct LaunchArgs {
     // distance evaluations per workgroup (one counter per workgroup), or null
     unsigned long long *evals;
     uint32_t strag[3];            // straggler thresholds by split_bucket(m)
+    // 1: the queue holds local and triple items only, and the launch uses the
+    // main kernel compiled for those (fewer registers, more workgroups per CU)
+    uint32_t local_only;
 };
 
 // A run of equally spaced queries of one series pair, expanded on the device

@@ -2384,8 +2384,12 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 // --------------------------------------------------------------------------
 // main: persistent loop over items
 // --------------------------------------------------------------------------
-template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 5 : 1))) void main_kernel(LaunchArgs a)
+// Two compilations per k: every item kind, at five workgroups per CU for k <=
+// 5; and, for queues of local and triple items only, those two paths alone,
+// whose smaller register need allows eight workgroups per CU (k <= 5).
+template <int K, bool LOCAL_ONLY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ? (LOCAL_ONLY ? 8 : 5) : 1))) void
+main_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
     __shared__ LocalShared L;
@@ -2414,7 +2418,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ?
         if (it >= a.n_items)
             break;
         const Item itm = a.item[a.item_begin + it];
-        if (itm.info & kItemSweep) {
+        if (LOCAL_ONLY) {
+            if (itm.info & kItemTriple)
+                triple_item<K>(a, itm.win, itm.info & 0xFFu, buf, T);
+            else if (itm.info & kItemLocal)
+                local_item<K>(a, itm.win, itm.info & 0xFFu, buf, L);
+            else if (tid == 0)
+                atomicOr(a.err, kErrItemKind);  // the host chose the wrong variant: report, skip
+        } else if (itm.info & kItemSweep) {
             if (!sweep_item<K>(a, itm.win, itm.info & 0xFFu, buf, SW)) {
                 // values too widely spread for 32-bit keys: every window on its own
                 for (uint32_t c = 0; c < (itm.info & 0xFFu); ++c) {
@@ -2765,21 +2776,27 @@ hipError_t noalloc_scratch(int device, void **ptr)
 #ifdef WMI_MAIN_K
 hipError_t WMI_PASTE(launch_main_k, WMI_MAIN_K)(const LaunchArgs &a, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(main_kernel<WMI_MAIN_K>, dim3(grid), dim3(kBlock), 0, s, a);
+    if (a.local_only)
+        hipLaunchKernelGGL((main_kernel<WMI_MAIN_K, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((main_kernel<WMI_MAIN_K, false>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
-int WMI_PASTE(main_occupancy_k, WMI_MAIN_K)()
+int WMI_PASTE(main_occupancy_k, WMI_MAIN_K)(bool local_only)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, main_kernel<WMI_MAIN_K>, kBlock, 0) != hipSuccess)
+    const hipError_t e =
+        local_only ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, main_kernel<WMI_MAIN_K, true>, kBlock, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, main_kernel<WMI_MAIN_K, false>, kBlock, 0);
+    if (e != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 #else
 #define X(KK)                                                                      \
     hipError_t launch_main_k##KK(const LaunchArgs &a, uint32_t grid, hipStream_t s); \
-    int main_occupancy_k##KK();
+    int main_occupancy_k##KK(bool local_only);
 WMI_K_CASES(X)
 #undef X
 
@@ -2798,12 +2815,12 @@ hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s)
     }
 }
 
-int main_occupancy(uint32_t k)
+int main_occupancy(uint32_t k, bool local_only)
 {
     switch (k) {
 #define X(KK) \
     case KK:  \
-        return main_occupancy_k##KK();
+        return main_occupancy_k##KK(local_only);
         WMI_K_CASES(X)
 #undef X
     default:

@@ -353,7 +353,7 @@ int finish_if_done(wmi_batch *b, bool block, int64_t timeout_us)
         uint32_t err = 0;
         std::memcpy(&err, reinterpret_cast<const char *>(b->h_res) + b->count * sizeof(Result), sizeof err);
         if (err)
-            return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
+            return fail(WMI_EHIP, "device reported internal error 0x%x (1: a dependency wait gave up; 2: an item the kernel variant does not run)", err);
     }
     return WMI_OK;
 }
@@ -691,6 +691,7 @@ struct BatchBuild {
     std::vector<uint64_t> wx, wy;  // address of each window's first x and y value
     std::vector<RangeDesc> rd;     // runs of queries (wmi_submit_ranges): the descriptor prefix
     bool ranged = false;
+    bool local_only = false;       // local and triple items only: the lighter kernel variant
     Tuning tune;
     uint64_t pairs = 0, n_win = 0, n_items = 0, n_prep = 0;
     bool plain = false;
@@ -745,8 +746,14 @@ int build_batch(wmi_store *st, const wmi_query *qs, uint64_t count, const wmi_pa
     // ---- work items ---------------------------------------------------------
     B.plain = (p->flags & WMI_SUBMIT_PLAIN) != 0;
     plan_items(B.wm, B.wquery, count, B.plain, B.plan, !(p->flags & WMI_SUBMIT_NO_REUSE), &B.wx, &B.wy, &B.tune);
-    if (!B.plain)
+    if (!B.plain) {
         plan_queue(B.plan, B.wm, B.queue);
+        // the lighter variant gains occupancy for k <= 5 only
+        B.local_only = p->k <= 5 && std::all_of(B.queue.begin(), B.queue.end(), [](const Item &it) {
+            const uint32_t top = it.info & 0xF0000000u;
+            return top == kItemLocal || top == kItemTriple;
+        });
+    }
     B.n_items = B.plain ? B.plan.items.size() : B.queue.size();
     B.n_prep = B.plan.prep_list.size();
     if (B.plan.split_pts > 0xFFFFFFF0ull)
@@ -859,6 +866,8 @@ int build_ranges(wmi_store *st, const wmi_range *rg, uint64_t n_ranges, const wm
                     (unsigned long long)B.plan.split_pts);
     B.n_prep = 0;
     B.plain = false;
+    B.local_only = p->k <= 5 && std::all_of(B.rd.begin(), B.rd.end(),
+                               [](const RangeDesc &R) { return R.kind == kRangeLocal || R.kind == kRangeTriple; });
     layout_batch(B, total, p);
     *count = total;
     return WMI_OK;
@@ -933,6 +942,7 @@ void set_args(const BatchBuild &B, const wmi_store *st, const wmi_params *p, uin
     a.win_begin = 0;
     for (int i = 0; i < 3; ++i)
         a.strag[i] = B.tune.stragglers[i];
+    a.local_only = B.local_only ? 1u : 0u;
 }
 
 // The entropy pass over a device buffer laid out as B: all windows' entropies
@@ -1043,7 +1053,7 @@ int start_batch(wmi_store *st, BatchBuild &B, const wmi_query *qs, uint64_t coun
         b->h_hres = reinterpret_cast<const double *>(b->host + desc_bytes + (B.o_hres - B.o_res));
     }
     set_entropy_args(B, p, count, b->dev, d_hres, b->eargs);
-    int occ = main_occupancy(p->k);
+    int occ = main_occupancy(p->k, B.local_only);
     uint64_t slots = (uint64_t)st->cu_count * (uint64_t)occ;
     b->grid = (uint32_t)std::min<uint64_t>(B.n_items, slots);
     b->stats.items = (uint32_t)B.n_items;
@@ -1167,7 +1177,7 @@ int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const
     EntropyArgs ea;
     set_entropy_args(B, p, count, dev, nullptr, ea);
     const uint32_t grid =
-        (uint32_t)std::min<uint64_t>(B.n_items, (uint64_t)st->cu_count * (uint64_t)main_occupancy(p->k));
+        (uint32_t)std::min<uint64_t>(B.n_items, (uint64_t)st->cu_count * (uint64_t)main_occupancy(p->k, B.local_only));
     hipStream_t s = stream ? (hipStream_t)stream : st->stream;
     uint32_t err = 0;
     hipError_t e = hipMemcpyAsync(dev, host.data(), B.desc_bytes, hipMemcpyHostToDevice, s);
@@ -1185,7 +1195,7 @@ int wmi_submit_noalloc(wmi_store *st, const wmi_query *qs, uint64_t count, const
     if (e != hipSuccess)
         return poison(st, e, "wmi_submit_noalloc");
     if (err)
-        return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
+        return fail(WMI_EHIP, "device reported internal error 0x%x (1: a dependency wait gave up; 2: an item the kernel variant does not run)", err);
     return WMI_OK;
 }
 
@@ -1351,7 +1361,7 @@ int wmi_batch_count_evals(wmi_batch *b, uint64_t *evaluated)
     if (e != hipSuccess)
         return poison(st, e, "wmi_batch_count_evals");
     if (err)
-        return fail(WMI_EHIP, "device reported internal error 0x%x (a dependency wait gave up)", err);
+        return fail(WMI_EHIP, "device reported internal error 0x%x (1: a dependency wait gave up; 2: an item the kernel variant does not run)", err);
     uint64_t total = 0;
     for (unsigned long long v : h)
         total += v;

@@ -56,7 +56,7 @@ hipError_t launch_main(const LaunchArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_validate(const float *v, uint64_t n, unsigned long long *bad, hipStream_t s);
 hipError_t launch_expand(const LaunchArgs &a, const PartDesc *parts, uint32_t n_parts, Item *queue, WinDesc *win,
                          QDesc *qd, uint64_t *cdst, hipStream_t s);
-int main_occupancy(uint32_t k);
+int main_occupancy(uint32_t k, bool local_only = false);
 // Device address of the allocation-free entry point's scratch array on
 // `device` (which must be current); looked up once per device.
 hipError_t noalloc_scratch(int device, void **ptr);

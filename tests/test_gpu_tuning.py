@@ -118,3 +118,26 @@ def test_bad_tuning_rejected(wmi):
                 st.set_tuning(bad)
         st.set_tuning(None)
         assert st.get_tuning()["local_windows"] == [16] * 5
+
+
+def test_kernel_variants_agree(wmi):
+    """Queues of local and triple items run on the lighter compilation of the
+    main kernel (more workgroups per CU); adding one large window moves the
+    same queries onto the general one.  Results must be bit-identical."""
+    series, q = workload()
+    small = q[(q["len"] + q["ext_len"]) <= 512]
+    small = small[small["ext_side"] != 0][:3000]
+    small = np.concatenate([small, q[(q["ext_side"] == 0) & (q["len"] <= 256)][:3000]])
+    big = synth.make_queries(0, 1, np.array([100], dtype=np.uint64), 2000)
+    with wmi.Store(0) as st:
+        assert [st.add_series(s) for s in series] == [0, 1]
+        for k in (4, 3):
+            b1 = st.submit(small, k=k, tau=0.05)
+            r1, s1 = b1.read(), b1.stats()
+            b1.destroy()
+            b2 = st.submit(np.concatenate([small, big]), k=k, tau=0.05)
+            r2, s2 = b2.read(), b2.stats()
+            b2.destroy()
+            assert np.array_equal(r1.view(np.uint8), r2[:len(small)].view(np.uint8))
+            assert s1["wg_per_cu"] > s2["wg_per_cu"], (s1["wg_per_cu"], s2["wg_per_cu"])
+            log(f"k={k}: {len(small)} queries, {s1['wg_per_cu']} vs {s2['wg_per_cu']} workgroups per CU, identical")
