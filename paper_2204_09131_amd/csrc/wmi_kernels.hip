@@ -2388,7 +2388,7 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 // 5; and, for queues of local and triple items only, those two paths alone,
 // whose smaller register need allows eight workgroups per CU (k <= 5).
 template <int K, bool LOCAL_ONLY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ? (LOCAL_ONLY ? 8 : 5) : 1))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 5 ? (LOCAL_ONLY ? 8 : 4) : 1))) void
 main_kernel(LaunchArgs a)
 {
     __shared__ __align__(16) uint32_t buf[2 * kChunk];  // 16 KB, shared by both item kinds
