@@ -1606,7 +1606,15 @@ struct TripleShared {
     int32_t mx[2][kTripleMax];
     unsigned long long acc[kTripleMax][3];    // base, extension, union
     uint32_t P, log2P;
+    uint32_t njobs;                           // part counts handed to other threads
 };
+
+// Part counts of the larger part's points whose part radii differ from their
+// union radii (their part list lost a neighbour to the other part) are
+// searched by other threads, one job per thread: four words per job (the
+// point as t | i << 8, its part radii; then its four counts), in the LDS words
+// the union keys leave free.  The other points reuse their union counts.
+constexpr int kTripJobs = kBlock;
 
 // Scan candidates j = j0 + jj, jj in [0, n), of a thread's union (cw: its
 // keys, two words per point) for the thread's two query points into the
@@ -1723,6 +1731,8 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         T.b0[tid] = (uint32_t)(de.x - du.x);
         T.nb[tid] = de.m;
         T.flags[tid] = 0u;
+        if (tid == 0)
+            T.njobs = 0u;
         T.mn[0][tid] = INT32_MAX;
         T.mn[1][tid] = INT32_MAX;
         T.mx[0][tid] = INT32_MIN;
@@ -1913,19 +1923,82 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
     bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, ntrip << lp, P);
 
     // ---- counts and digamma terms
+    // union counts: two searches per dimension and point; a larger-part
+    // point's part counts equal them when its part radii equal its union
+    // radii, else they come from a job
+    const bool small_a = na <= nbp;
+    const int s0 = small_a ? a0 : b0, ns = small_a ? na : nbp;
+    int cx[8], cy[8];
+    int job[2] = {-1, -1};
+    uint32_t *jobs = buf + 2 * kLocalSlots;  // the words after the union keys
     if (live) {
         const int32_t *sx = srt_x + (t << lp), *sy = srt_y + (t << lp);
-        // the smaller part, counted by brute force
-        const bool small_a = na <= nbp;
-        const int s0 = small_a ? a0 : b0, ns = small_a ? na : nbp;
-        int32_t vx[8], vy[8];
-        int cx[8], cy[8];
+        int32_t vx[4], vy[4];
+        int ux[4], uy[4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            count_bounds(a.estimator, X[q], Y[q], (int32_t)RXu[q], (int32_t)RYu[q], vx + 2 * q, vy + 2 * q);
+        count_lt_xy<4>(sx, sy, m, vx, vy, ux, uy);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            count_bounds(a.estimator, X[q], Y[q], (int32_t)RXu[q], (int32_t)RYu[q], vx + 4 * q, vy + 4 * q);
-            count_bounds(a.estimator, X[q], Y[q], (int32_t)RXp[q], (int32_t)RYp[q], vx + 4 * q + 2, vy + 4 * q + 2);
+            cx[4 * q] = ux[2 * q];
+            cx[4 * q + 1] = ux[2 * q + 1];
+            cy[4 * q] = uy[2 * q];
+            cy[4 * q + 1] = uy[2 * q + 1];
+            cx[4 * q + 2] = cx[4 * q];
+            cx[4 * q + 3] = cx[4 * q + 1];
+            cy[4 * q + 2] = cy[4 * q];
+            cy[4 * q + 3] = cy[4 * q + 1];
+            const bool inA = q == 0 ? inA0 : inA1;
+            const bool in_small = small_a ? inA : !inA;
+            const int part_m = inA ? na : nbp;
+            if (act[q] && part_m > K && !in_small && (RXp[q] != RXu[q] || RYp[q] != RYu[q])) {
+                const uint32_t j = atomicAdd(&T.njobs, 1u);
+                if (j < (uint32_t)kTripJobs) {
+                    jobs[4 * j] = t | ((uint32_t)(I[0] + q) << 8);
+                    jobs[4 * j + 1] = RXp[q];
+                    jobs[4 * j + 2] = RYp[q];
+                    job[q] = (int)j;
+                } else {
+                    // more jobs than threads: search here
+                    int32_t wx[2], wy[2];
+                    int px[2], py[2];
+                    count_bounds(a.estimator, X[q], Y[q], (int32_t)RXp[q], (int32_t)RYp[q], wx, wy);
+                    count_lt_xy<2>(sx, sy, m, wx, wy, px, py);
+                    cx[4 * q + 2] = px[0];
+                    cx[4 * q + 3] = px[1];
+                    cy[4 * q + 2] = py[0];
+                    cy[4 * q + 3] = py[1];
+                }
+            }
         }
-        count_lt_xy<8>(sx, sy, m, vx, vy, cx, cy);
+    }
+    block_sync();
+    if ((uint32_t)tid < min(T.njobs, (uint32_t)kTripJobs)) {
+        const uint32_t w0 = jobs[4 * tid], jt = w0 & 0xFFu, ji = w0 >> 8;
+        const uint32_t nbj = T.bits[jt];
+        const uint32_t *cj = cand + 2 * (T.off[jt] + ji);
+        const int32_t xj = (int32_t)(cj[0] >> nbj) + T.mn[0][jt], yj = (int32_t)(cj[1] >> nbj) + T.mn[1][jt];
+        int32_t wx[2], wy[2];
+        int px[2], py[2];
+        count_bounds(a.estimator, xj, yj, (int32_t)jobs[4 * tid + 1], (int32_t)jobs[4 * tid + 2], wx, wy);
+        count_lt_xy<2>(srt_x + (jt << lp), srt_y + (jt << lp), (int)T.m[jt], wx, wy, px, py);
+        jobs[4 * tid] = (uint32_t)px[0];
+        jobs[4 * tid + 1] = (uint32_t)px[1];
+        jobs[4 * tid + 2] = (uint32_t)py[0];
+        jobs[4 * tid + 3] = (uint32_t)py[1];
+    }
+    block_sync();
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (job[q] >= 0) {
+                cx[4 * q + 2] = (int)jobs[4 * job[q]];
+                cx[4 * q + 3] = (int)jobs[4 * job[q] + 1];
+                cy[4 * q + 2] = (int)jobs[4 * job[q] + 2];
+                cy[4 * q + 3] = (int)jobs[4 * job[q] + 3];
+            }
+        }
         long long tu = 0, tpa = 0, tpb = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
