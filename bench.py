@@ -59,12 +59,12 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # workload name.
 TRAFFIC = {
     "cfg3_allpairs_64x32768_w256_s8_triples": {
-        "fetch_bytes": 314485424, "write_bytes": 1528980723,
-        "kernel_sha256": "176cad1055a20ee395d776c36b16d8e5ce0daea8a414d3c0aebc55454964a431",
+        "fetch_bytes": 1719975172, "write_bytes": 3657852446,
+        "kernel_sha256": "28ef2c30f66b6f4e19d550aabf668fa32f0a3a2feb4bb56561c7167fdc8a3270",
         "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
     "cfg2_multiscale_n65536_w32-4096_s8th": {
-        "fetch_bytes": 105265834, "write_bytes": 83407704,
-        "kernel_sha256": "176cad1055a20ee395d776c36b16d8e5ce0daea8a414d3c0aebc55454964a431",
+        "fetch_bytes": 67028988, "write_bytes": 37277387,
+        "kernel_sha256": "28ef2c30f66b6f4e19d550aabf668fa32f0a3a2feb4bb56561c7167fdc8a3270",
         "source": "profiles/main_kernel_cfg2_multiscale.md"},
 }
 
