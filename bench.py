@@ -55,11 +55,11 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # WRITE_SIZE passes (KiB per dispatch) over a workload's launches, each
 # scaled by what the same counter reads for an elementwise kernel of known
 # traffic (256 MiB read, 256 MiB written).  Valid only for the kernel source
-# it was taken on (hash of the kernel and descriptor sources); keyed by
-# workload name.
+# it was taken on (hash of the kernel and descriptor sources) and for the
+# launch shape it was taken with (batches per pass); keyed by workload name.
 TRAFFIC = {
     "cfg3_allpairs_64x32768_w256_s8_triples": {
-        "fetch_bytes": 1719975172, "write_bytes": 3657852446,
+        "fetch_bytes": 1719975172, "write_bytes": 3657852446, "batches_per_pass": 16,
         "kernel_sha256": "28ef2c30f66b6f4e19d550aabf668fa32f0a3a2feb4bb56561c7167fdc8a3270",
         "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
     "cfg2_multiscale_n65536_w32-4096_s8th": {
@@ -78,9 +78,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def traffic_of(workload: str):
+def traffic_of(workload: str, batches_per_pass: int = 1):
     t = TRAFFIC.get(workload)
     if not t or t["kernel_sha256"] != kernel_source_hash():
+        return None
+    if t.get("batches_per_pass", 1) != batches_per_pass:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -147,7 +149,7 @@ def sample_pairs(q) -> float:
 
 
 # batches of the headline pass (runs of whole pairs); alternating streams
-HEADLINE_BATCHES = 16
+HEADLINE_BATCHES = 8
 
 
 def frac(ops, seconds) -> float:
@@ -215,7 +217,7 @@ def headline(args, wmi, torch, w) -> dict:
             "evaluated": evaluated, "pairs": pairs, "noise_triples": noise,
             "roofline": {"bound": "alu", "kernel": "main_kernel<4>", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                          "unit": "TOP/s", "frac": None if achieved is None else achieved / VALU_PEAK_TOPS,
-                         "traffic": traffic_of(w.name),
+                         "traffic": traffic_of(w.name, HEADLINE_BATCHES),
                          "traffic_unit": "HBM bytes per launch (fetch + write, calibrated counters)",
                          "ops_per_distance": OPS_PER_PAIR, "launches_per_step": launches,
                          "distances_per_launch": None if evaluated is None else evaluated / launches,
@@ -336,7 +338,8 @@ def multiscale(args, wmi, torch, synth) -> dict:
            "brute_force_pairs_per_s": pairs / (ms_step / 1e3),
            "main_kernel": {"evaluated_distances": int(evaluated), "evaluated_share": evaluated / pairs,
                            "achieved_tops": OPS_PER_PAIR * evaluated / main_s / 1e12,
-                           "frac_valu_peak": frac(OPS_PER_PAIR * evaluated, main_s)},
+                           "frac_valu_peak": frac(OPS_PER_PAIR * evaluated, main_s),
+                           "hbm_traffic_bytes": traffic_of(w.name)},
            "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                 "samples": int(len(lat)), "what": "fresh submit of the whole batch to results on host"},
            "as_runs": runs,

@@ -446,7 +446,10 @@ __device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_
                 dst[s] = (int32_t)buf[s] + mn;
         }
     }
-    __threadfence();
+    // release only: write this window's sorted data back to memory before
+    // the flag is raised (the acquire half would needlessly invalidate the
+    // caches the rest of the CU's work is using)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     block_sync();
     if (threadIdx.x == 0)
         atomicExch(&a.ready[w], kReady | (ax.flags ? kReadyOffGrid : 0u) | (ax.nb << kReadyNbShift));
@@ -663,7 +666,9 @@ __device__ WinAux split_window_aux(const LaunchArgs &a, uint32_t w, const WinDes
         s_red[0] = (int32_t)v;
     }
     block_sync();
-    __threadfence();  // acquire: later loads see the prep item's stores
+    // acquire only (the reader has nothing to release): later loads see
+    // the prep item's stores
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t v = (uint32_t)s_red[0];
     const int m = (int)d.m;
     const int32_t *base = a.sorted + (uint64_t)kSortedWords * d.sorted_off;
