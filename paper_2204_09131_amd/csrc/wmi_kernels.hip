@@ -88,6 +88,11 @@ __device__ __forceinline__ uint32_t sad_key_v(uint32_t a, uint32_t b, uint32_t c
     return r;
 }
 
+// Global loads a thread keeps in flight in the staging loops of the window
+// sorts and the split items: each loop issues this many before using any, so
+// a window costs one memory latency per batch rather than one per element.
+constexpr int kLoadBatch = 8;
+
 // Workgroup barrier after this wave's LDS accesses have completed.  The
 // wait is explicit: the compiler's own wait before a barrier at the head of
 // a loop (reached along the back edge from LDS stores) was found missing, and
@@ -332,6 +337,123 @@ __device__ void bitonic_lds(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
     block_sync();
 }
 
+// Signed median of three: med3_i32(a, b, INT32_MIN) = min(a, b) and
+// med3_i32(a, b, INT32_MAX) = max(a, b), so one instruction keeps either
+// side of a compare-exchange.
+__device__ __forceinline__ int32_t med3_i32(int32_t a, int32_t b, int32_t c)
+{
+    int32_t r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// The value of lane (lane ^ X) of the wave, X < 64: a swizzle in bit-mask
+// mode within each half-wave (and mask 31, xor mask X), a permute across
+// halves for X = 32.
+template <int X>
+__device__ __forceinline__ int32_t xor_lane(int32_t v)
+{
+    if constexpr (X == 32)
+        return __shfl_xor(v, 32, 64);
+    else
+        return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
+}
+
+// One compare-exchange stage of the register bitonic sort at element
+// distance 2X (lane distance X), for both arrays and both elements of the
+// thread: bound INT32_MIN keeps the smaller value, INT32_MAX the larger.
+template <int X>
+__device__ __forceinline__ void bitonic_lane_stage(int32_t (&va)[2], int32_t (&vb)[2], int32_t bound)
+{
+    const int32_t pa0 = xor_lane<X>(va[0]), pa1 = xor_lane<X>(va[1]);
+    const int32_t pb0 = xor_lane<X>(vb[0]), pb1 = xor_lane<X>(vb[1]);
+    va[0] = med3_i32(va[0], pa0, bound);
+    va[1] = med3_i32(va[1], pa1, bound);
+    vb[0] = med3_i32(vb[0], pb0, bound);
+    vb[1] = med3_i32(vb[1], pb1, bound);
+}
+
+// The same ascending segmented sort as bitonic_lds for total <= 2 kBlock
+// entries, with the data in registers: thread t holds entries 2t and 2t + 1
+// of both arrays.  A stage at distance 1 stays inside the thread, distances
+// 2..128 entries (lanes 1..64 of one wave) are exchanged by swizzles, and
+// only distances across waves go through LDS.  Each side of a pair computes
+// the kept value itself (min or max by the entry's position), one med3 per
+// entry.  Called by the whole workgroup after the arrays are staged; the
+// sorted arrays are back in LDS when it returns.
+__device__ void bitonic_regs(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
+{
+    const uint32_t e = 2u * threadIdx.x;  // this thread's first entry
+    const bool mine = e < total;
+    int32_t va[2], vb[2];
+    {
+        const int2 x = reinterpret_cast<const int2 *>(a)[threadIdx.x];
+        const int2 y = reinterpret_cast<const int2 *>(b)[threadIdx.x];
+        va[0] = x.x;
+        va[1] = x.y;
+        vb[0] = y.x;
+        vb[1] = y.y;
+    }
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        const bool asc = ((e & (P - 1u)) & size) == 0u;  // the same for both entries
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride == 1u) {
+                const int32_t lo = asc ? INT32_MIN : INT32_MAX, hi = asc ? INT32_MAX : INT32_MIN;
+                const int32_t a0 = med3_i32(va[0], va[1], lo), a1 = med3_i32(va[0], va[1], hi);
+                const int32_t b0 = med3_i32(vb[0], vb[1], lo), b1 = med3_i32(vb[0], vb[1], hi);
+                va[0] = a0;
+                va[1] = a1;
+                vb[0] = b0;
+                vb[1] = b1;
+                continue;
+            }
+            const bool lower = (e & stride) == 0u;
+            const int32_t bound = lower == asc ? INT32_MIN : INT32_MAX;
+            switch (stride) {
+            case 2: bitonic_lane_stage<1>(va, vb, bound); break;
+            case 4: bitonic_lane_stage<2>(va, vb, bound); break;
+            case 8: bitonic_lane_stage<4>(va, vb, bound); break;
+            case 16: bitonic_lane_stage<8>(va, vb, bound); break;
+            case 32: bitonic_lane_stage<16>(va, vb, bound); break;
+            case 64: bitonic_lane_stage<32>(va, vb, bound); break;
+            default: {
+                // across waves: through LDS (the partner pair is adjacent too)
+                block_sync();  // earlier reads of the arrays are complete
+                if (mine) {
+                    reinterpret_cast<int2 *>(a)[threadIdx.x] = make_int2(va[0], va[1]);
+                    reinterpret_cast<int2 *>(b)[threadIdx.x] = make_int2(vb[0], vb[1]);
+                }
+                block_sync();
+                const uint32_t pe = (e ^ stride) >> 1;  // e < 2 kBlock, stride < 2 kBlock: in the arrays
+                const int2 x = reinterpret_cast<const int2 *>(a)[pe];
+                const int2 y = reinterpret_cast<const int2 *>(b)[pe];
+                va[0] = med3_i32(va[0], x.x, bound);
+                va[1] = med3_i32(va[1], x.y, bound);
+                vb[0] = med3_i32(vb[0], y.x, bound);
+                vb[1] = med3_i32(vb[1], y.y, bound);
+            }
+            }
+        }
+    }
+    block_sync();  // every read of the last LDS stage is complete
+    if (mine) {
+        reinterpret_cast<int2 *>(a)[threadIdx.x] = make_int2(va[0], va[1]);
+        reinterpret_cast<int2 *>(b)[threadIdx.x] = make_int2(vb[0], vb[1]);
+    }
+    block_sync();
+}
+
+// Segmented ascending sort of the marginals staged in LDS (segments of P
+// entries, total a multiple of P, at most kLocalSort): in registers when
+// every entry has a thread, else through LDS.
+__device__ __forceinline__ void sort_marginals(int32_t *a, int32_t *b, uint32_t total, uint32_t P)
+{
+    if (total <= 2u * kBlock)
+        bitonic_regs(a, b, total, P);
+    else
+        bitonic_lds<kLocalSort / (2 * kBlock), 2>(a, b, total, P);
+}
+
 __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red);
 
 // Stable LSD radix sort of the n <= kMaxWindow words a[0, n) in LDS on bits
@@ -431,14 +553,39 @@ __device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_
         const uint32_t shift = job ? 0u : ax.nb;
         uint32_t off = 0;
         block_sync();
-        for (int i = tid; i < m; i += kBlock)
-            buf[i] = ((uint32_t)(grid_int(v[i], off) - mn) << shift) | (shift ? (uint32_t)i : 0u);
+        for (int i0 = tid; i0 < m; i0 += kLoadBatch * kBlock) {
+            float vv[kLoadBatch];
+#pragma unroll
+            for (int g = 0; g < kLoadBatch; ++g)
+                vv[g] = v[i0 + g * kBlock < m ? i0 + g * kBlock : i0];
+#pragma unroll
+            for (int g = 0; g < kLoadBatch; ++g) {
+                const int i = i0 + g * kBlock;
+                if (i < m)
+                    buf[i] = ((uint32_t)(grid_int(vv[g], off) - mn) << shift) | (shift ? (uint32_t)i : 0u);
+            }
+        }
         radix_lds(buf, m, (int)shift, (value_bits(job ? ax.range_y : ax.range_x) + 3) / 4, s_cnt);
         if (shift) {
-            for (int s = tid; s < m; s += kBlock) {
-                const uint32_t key = buf[s];
-                out[s] = (int32_t)key;
-                out[m + s] = (int32_t)((uint32_t)(grid_int(d.y[key & mask], off) - ax.min_y) << ax.nb);
+            // beside each x-order key the y key of its point: a gather,
+            // kLoadBatch loads in flight per thread
+            for (int s0 = tid; s0 < m; s0 += kLoadBatch * kBlock) {
+                uint32_t key[kLoadBatch];
+                float yv[kLoadBatch];
+#pragma unroll
+                for (int g = 0; g < kLoadBatch; ++g)
+                    key[g] = buf[s0 + g * kBlock < m ? s0 + g * kBlock : s0];
+#pragma unroll
+                for (int g = 0; g < kLoadBatch; ++g)
+                    yv[g] = d.y[key[g] & mask];
+#pragma unroll
+                for (int g = 0; g < kLoadBatch; ++g) {
+                    const int s = s0 + g * kBlock;
+                    if (s < m) {
+                        out[s] = (int32_t)key[g];
+                        out[m + s] = (int32_t)((uint32_t)(grid_int(yv[g], off) - ax.min_y) << ax.nb);
+                    }
+                }
             }
         } else {
             int32_t *dst = job ? out + 2 * m : out;
@@ -607,12 +754,22 @@ __device__ WinAux window_aux(const WinDesc &d, int32_t *s_red)
     block_sync();
     int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
     uint32_t off = 0;
-    for (int i = tid; i < m; i += kBlock) {
-        const int32_t xi = grid_int(d.x[i], off), yi = grid_int(d.y[i], off);
-        mnx = min(mnx, xi);
-        mxx = max(mxx, xi);
-        mny = min(mny, yi);
-        mxy = max(mxy, yi);
+    for (int i0 = tid; i0 < m; i0 += kLoadBatch * kBlock) {
+        float vx[kLoadBatch], vy[kLoadBatch];
+#pragma unroll
+        for (int g = 0; g < kLoadBatch; ++g) {
+            const int i = i0 + g * kBlock < m ? i0 + g * kBlock : i0;  // past the end: a repeat
+            vx[g] = d.x[i];
+            vy[g] = d.y[i];
+        }
+#pragma unroll
+        for (int g = 0; g < kLoadBatch; ++g) {
+            const int32_t xi = grid_int(vx[g], off), yi = grid_int(vy[g], off);
+            mnx = min(mnx, xi);
+            mxx = max(mxx, xi);
+            mny = min(mny, yi);
+            mxy = max(mxy, yi);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         mnx = min(mnx, __shfl_xor(mnx, o, 64));
@@ -871,10 +1028,18 @@ __device__ __forceinline__ void stage_wave(uint4 *wb, const uint32_t *KX, const 
 {
     const int lane = threadIdx.x & 63;
     asm volatile("" ::: "memory");
-    for (int i = lane; i < cnt; i += 64) {
-        const uint32_t key = KX[c0 + i];
-        wb[i] = make_uint4(key & ~mask, YS[c0 + i], key & mask, 0u);
+    static_assert(kWaveChunk == 128, "two candidates per lane");
+    uint32_t key[2], ys[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int i = lane + 64 * g < cnt ? lane + 64 * g : 0;  // cnt >= 1
+        key[g] = KX[c0 + i];
+        ys[g] = YS[c0 + i];
     }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+        if (lane + 64 * g < cnt)
+            wb[lane + 64 * g] = make_uint4(key[g] & ~mask, ys[g], key[g] & mask, 0u);
     // the chunk is written by the whole wave before any lane reads it
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
 }
@@ -1161,9 +1326,22 @@ __device__ long long split_body_sorted(const LaunchArgs &a, uint32_t w, const Wi
     for (int c0 = 0; c0 < m; c0 += kChunk) {
         const int cn = min(kChunk, m - c0);
         block_sync();
-        for (int i = tid; i < cn; i += kBlock) {
-            sx[i] = KX[c0 + i];
-            sy[i] = SY[c0 + i];
+        for (int i0 = tid; i0 < cn; i0 += kLoadBatch * kBlock) {
+            uint32_t kx[kLoadBatch];
+            int32_t ky[kLoadBatch];
+#pragma unroll
+            for (int g = 0; g < kLoadBatch; ++g) {
+                const int i = i0 + g * kBlock < cn ? i0 + g * kBlock : i0;
+                kx[g] = KX[c0 + i];
+                ky[g] = SY[c0 + i];
+            }
+#pragma unroll
+            for (int g = 0; g < kLoadBatch; ++g) {
+                if (i0 + g * kBlock < cn) {
+                    sx[i0 + g * kBlock] = kx[g];
+                    sy[i0 + g * kBlock] = ky[g];
+                }
+            }
         }
         block_sync();
         int cxs[4], cys[4];
@@ -1518,7 +1696,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     block_sync();
 
     // ---- sort every window's marginals (segments of P, padded with INT32_MAX)
-    bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, nwin << lp, P);
+    sort_marginals(srt_x, srt_y, nwin << lp, P);
 
     // ---- counts and digamma terms: both slots of a thread lie in one window,
     // so their eight searches run interleaved over the same sorted marginals
@@ -1925,7 +2103,7 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
     block_sync();
 
     // ---- sort every union's marginals (segments of P, padded with INT32_MAX)
-    bitonic_lds<kLocalSort / (2 * kBlock), 2>(srt_x, srt_y, ntrip << lp, P);
+    sort_marginals(srt_x, srt_y, ntrip << lp, P);
 
     // ---- counts and digamma terms
     // union counts: two searches per dimension and point; a larger-part
