@@ -703,17 +703,18 @@ __device__ __forceinline__ void radii_k(const T (&nbk)[K], int shift, uint32_t m
                                         uint32_t &rx, uint32_t &ry)
 {
     if (est == 0) {
+        // in key units: coordinates carry dshift zero bits, so the distance
+        // is shifted back once at the end
         uint32_t ex = 0, ey = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            uint32_t jj = min((uint32_t)(nbk[r] & (T)mask), (uint32_t)(m - 1));
-            uint32_t cx = cand[2 * (base + jj)] >> dshift, cy = cand[2 * (base + jj) + 1] >> dshift;
-            uint32_t px = qx >> dshift, py = qy >> dshift;
-            ex = tmax(ex, px > cx ? px - cx : cx - px);
-            ey = tmax(ey, py > cy ? py - cy : cy - py);
+            const uint32_t jj = min((uint32_t)(nbk[r] & (T)mask), (uint32_t)(m - 1));
+            const uint2 c = reinterpret_cast<const uint2 *>(cand)[base + jj];
+            ex = tmax(ex, sad_u32(qx, c.x, 0u));
+            ey = tmax(ey, sad_u32(qy, c.y, 0u));
         }
-        rx = ex;
-        ry = ey;
+        rx = ex >> dshift;
+        ry = ey >> dshift;
     } else {
         rx = (uint32_t)(nbk[K - 1] >> shift);
         ry = rx;
@@ -1672,21 +1673,19 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             const int m = (int)L.m[wl];
             const uint32_t nb = L.nb[wl];
             // wave-wide: one window?  same m everywhere?  any 64-bit window?
-            int m_max = m, m_min = m, w_min = (int)wl, w_max = (int)wl, i_min = il;
-            uint32_t nb_min = nb;
-            for (int o = 32; o > 0; o >>= 1) {
-                m_max = max(m_max, __shfl_xor(m_max, o, 64));
-                m_min = min(m_min, __shfl_xor(m_min, o, 64));
-                w_min = min(w_min, __shfl_xor(w_min, o, 64));
-                w_max = max(w_max, __shfl_xor(w_max, o, 64));
-                i_min = min(i_min, __shfl_xor(i_min, o, 64));
-                nb_min = min(nb_min, (uint32_t)__shfl_xor((int)nb_min, o, 64));
+            // (against lane 0, which holds a live slot's window); slots rise
+            // with the lane inside a window, so with one window the wave's
+            // lowest slot is the first live lane's
+            const bool one_win = __ballot(wl != (uint32_t)__builtin_amdgcn_readfirstlane((int)wl)) == 0ull;
+            const bool one_m = __ballot(m != __builtin_amdgcn_readfirstlane(m)) == 0ull;
+            const int mode = __ballot(nb == 0u) != 0ull ? 3 : (one_win ? 0 : (one_m ? 1 : 2));
+            const int band0 = __builtin_amdgcn_readfirstlane(lead_i);
+            int m_max = m;
+            if (!one_m) {
+                for (int o = 32; o > 0; o >>= 1)
+                    m_max = max(m_max, __shfl_xor(m_max, o, 64));
             }
-            // the reductions leave the same value in every lane: make that explicit
             m_max = __builtin_amdgcn_readfirstlane(m_max);
-            const int band0 = __builtin_amdgcn_readfirstlane(i_min);
-            const int mode = __builtin_amdgcn_readfirstlane(
-                nb_min == 0u ? 3 : (w_min == w_max ? 0 : (m_max == m_min ? 1 : 2)));
             local_knn2<K>(cand, L.off[wl], m, il, nb, mode, m_max, band0, a.estimator, RX, RY);
             // each live slot needs the m - 1 other points of its own window;
             // candidates a wave scans past a lane's window are padding
@@ -2020,22 +2019,14 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
             const uint32_t bitsl = T.bits[tl];
             const uint32_t *cwl = cand + 2 * T.off[tl];
             const int il = live ? I[0] : __shfl(I[0], first, 64);
-            // one shape in the whole wave (every triple of the wave alike)?
-            int v_min[5] = {ml, a0l, nal, b0l, nbl}, v_max[5] = {ml, a0l, nal, b0l, nbl};
-            uint32_t bits_min = bitsl;
-            for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                for (int r = 0; r < 5; ++r) {
-                    v_min[r] = min(v_min[r], __shfl_xor(v_min[r], o, 64));
-                    v_max[r] = max(v_max[r], __shfl_xor(v_max[r], o, 64));
-                }
-                bits_min = min(bits_min, (uint32_t)__shfl_xor((int)bits_min, o, 64));
-            }
-            bool uniform = true;
-#pragma unroll
-            for (int r = 0; r < 5; ++r)
-                uniform = uniform && v_min[r] == v_max[r];
-            const int mode = __builtin_amdgcn_readfirstlane(bits_min == 0u ? 2 : (uniform ? 0 : 1));
+            // one shape in the whole wave (every triple of the wave alike as
+            // lane 0's, which holds a live slot's union)?  any 64-bit union?
+            const bool alike = ml == __builtin_amdgcn_readfirstlane(ml) &&
+                               a0l == __builtin_amdgcn_readfirstlane(a0l) &&
+                               nal == __builtin_amdgcn_readfirstlane(nal) &&
+                               b0l == __builtin_amdgcn_readfirstlane(b0l) &&
+                               nbl == __builtin_amdgcn_readfirstlane(nbl);
+            const int mode = __ballot(bitsl == 0u) != 0ull ? 2 : (__ballot(!alike) == 0ull ? 0 : 1);
             const bool in0 = il >= a0l && il < a0l + nal, in1 = il + 1 >= a0l && il + 1 < a0l + nal;
             const uint32_t maskl = (1u << bitsl) - 1u;
             if (mode != 2) {
@@ -2056,14 +2047,22 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
                     }
                     trip_scan<S, false, true>(cwl, B0, NB, NB, qx0, qy0, qx1, qy1, !in0, !in1, u0, u1, p0, p1);
                 } else {
-                    trip_scan<S, true, false>(cwl, a0l, v_max[2], nal, qx0, qy0, qx1, qy1, false, false, u0, u1, p0,
+                    // the wave's loops run to its longest part
+                    int na_max = nal, nb_max = nbl;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        na_max = max(na_max, __shfl_xor(na_max, o, 64));
+                        nb_max = max(nb_max, __shfl_xor(nb_max, o, 64));
+                    }
+                    na_max = __builtin_amdgcn_readfirstlane(na_max);
+                    nb_max = __builtin_amdgcn_readfirstlane(nb_max);
+                    trip_scan<S, true, false>(cwl, a0l, na_max, nal, qx0, qy0, qx1, qy1, false, false, u0, u1, p0,
                                               p1);
 #pragma unroll
                     for (int r = 0; r < S; ++r) {
                         p0[r] = in0 ? u0[r] : 0xFFFFFFFFu;
                         p1[r] = in1 ? u1[r] : 0xFFFFFFFFu;
                     }
-                    trip_scan<S, true, true>(cwl, b0l, v_max[4], nbl, qx0, qy0, qx1, qy1, !in0, !in1, u0, u1, p0, p1);
+                    trip_scan<S, true, true>(cwl, b0l, nb_max, nbl, qx0, qy0, qx1, qy1, !in0, !in1, u0, u1, p0, p1);
                 }
                 const uint32_t bb = T.off[tl];
                 radii_from_keys<K, uint32_t>(u0, (uint32_t)il, (int)bitsl, maskl, ml, cand, bb, qx0, qy0, (int)bitsl,
