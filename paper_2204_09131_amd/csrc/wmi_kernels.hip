@@ -710,8 +710,8 @@ __device__ __forceinline__ void radii_k(const T (&nbk)[K], int shift, uint32_t m
         for (int r = 0; r < K; ++r) {
             const uint32_t jj = min((uint32_t)(nbk[r] & (T)mask), (uint32_t)(m - 1));
             const uint2 c = reinterpret_cast<const uint2 *>(cand)[base + jj];
-            ex = tmax(ex, sad_u32(qx, c.x, 0u));
-            ey = tmax(ey, sad_u32(qy, c.y, 0u));
+            ex = tmax(ex, sad_key(qx, c.x, 0u));
+            ey = tmax(ey, sad_key(qy, c.y, 0u));
         }
         rx = ex >> dshift;
         ry = ey >> dshift;
@@ -1575,10 +1575,6 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         L.query[tid] = d.query;
         L.acc[tid] = 0ull;
         L.flags[tid] = 0u;
-        L.mn[0][tid] = INT32_MAX;
-        L.mn[1][tid] = INT32_MAX;
-        L.mx[0][tid] = INT32_MIN;
-        L.mx[1][tid] = INT32_MIN;
     }
     block_sync();
     if (tid == 0) {
@@ -1621,10 +1617,6 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             Y[q] = grid_int(L.y[w][i], off);
             srt_x[(w << lp) + i] = X[q];
             srt_y[(w << lp) + i] = Y[q];
-            atomicMin(&L.mn[0][w], X[q]);
-            atomicMax(&L.mx[0][w], X[q]);
-            atomicMin(&L.mn[1][w], Y[q]);
-            atomicMax(&L.mx[1][w], Y[q]);
             if (off)
                 atomicOr(&L.flags[w], kFlagOffGrid);
         }
@@ -1637,8 +1629,17 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         }
     }
     block_sync();
+
+    // ---- sort every window's marginals (segments of P, padded with INT32_MAX):
+    // the counts search them, and their ends are the window's extrema
+    sort_marginals(srt_x, srt_y, nwin << lp, P);
     if (tid < (int)nwin) {
         const uint32_t m = L.m[tid];
+        const uint32_t last = m > 0u ? m - 1u : 0u;
+        L.mn[0][tid] = srt_x[tid << lp];
+        L.mx[0][tid] = srt_x[(tid << lp) + last];
+        L.mn[1][tid] = srt_y[tid << lp];
+        L.mx[1][tid] = srt_y[(tid << lp) + last];
         const uint32_t nb = ceil_log2(m > 1 ? m : 2u);
         const uint32_t rxr = (uint32_t)(L.mx[0][tid] - L.mn[0][tid]);
         const uint32_t ryr = (uint32_t)(L.mx[1][tid] - L.mn[1][tid]);
@@ -1693,9 +1694,6 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         }
     }
     block_sync();
-
-    // ---- sort every window's marginals (segments of P, padded with INT32_MAX)
-    sort_marginals(srt_x, srt_y, nwin << lp, P);
 
     // ---- counts and digamma terms: both slots of a thread lie in one window,
     // so their eight searches run interleaved over the same sorted marginals
@@ -1883,11 +1881,15 @@ __device__ __forceinline__ void trip_scan_wide(const uint32_t *__restrict__ cw, 
 __device__ __forceinline__ void trip_count_part(const uint32_t *__restrict__ cw, int s0, int ns, uint32_t qx,
                                                 uint32_t qy, uint32_t ex, uint32_t ey, uint32_t est, int &cx, int &cy)
 {
+    // |d| < e is |d| + 1 <= e on integers: the absolute difference carries
+    // the 1 for estimator 1 (no wrap: key coordinates stay below 2^32 - 1)
+    const uint32_t o = est == 0 ? 0u : 1u;
+    const uint2 *c2 = reinterpret_cast<const uint2 *>(cw);
     int nx = 0, ny = 0;
     for (int j = s0; j < s0 + ns; ++j) {
-        const uint32_t dx = sad_u32(qx, cw[2 * j], 0u), dy = sad_u32(qy, cw[2 * j + 1], 0u);
-        nx += est == 0 ? (dx <= ex) : (dx < ex);
-        ny += est == 0 ? (dy <= ey) : (dy < ey);
+        const uint2 c = c2[j];
+        nx += sad_key(qx, c.x, o) <= ex ? 1 : 0;
+        ny += sad_key(qy, c.y, o) <= ey ? 1 : 0;
     }
     cx = nx;
     cy = ny;
@@ -1915,10 +1917,6 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         T.flags[tid] = 0u;
         if (tid == 0)
             T.njobs = 0u;
-        T.mn[0][tid] = INT32_MAX;
-        T.mn[1][tid] = INT32_MAX;
-        T.mx[0][tid] = INT32_MIN;
-        T.mx[1][tid] = INT32_MIN;
         for (int r = 0; r < 3; ++r)
             T.acc[tid][r] = 0ull;
     }
@@ -1962,10 +1960,6 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
             Y[q] = grid_int(T.y[t][i], off);
             srt_x[(t << lp) + i] = X[q];
             srt_y[(t << lp) + i] = Y[q];
-            atomicMin(&T.mn[0][t], X[q]);
-            atomicMax(&T.mx[0][t], X[q]);
-            atomicMin(&T.mn[1][t], Y[q]);
-            atomicMax(&T.mx[1][t], Y[q]);
             if (off)
                 atomicOr(&T.flags[t], kFlagOffGrid);
         }
@@ -1978,8 +1972,17 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         }
     }
     block_sync();
+
+    // ---- sort every union's marginals (segments of P, padded with INT32_MAX):
+    // the counts search them, and their ends are the union's extrema
+    sort_marginals(srt_x, srt_y, ntrip << lp, P);
     if (tid < (int)ntrip) {
         const uint32_t m = T.m[tid];
+        const uint32_t last = m > 0u ? m - 1u : 0u;
+        T.mn[0][tid] = srt_x[tid << lp];
+        T.mx[0][tid] = srt_x[(tid << lp) + last];
+        T.mn[1][tid] = srt_y[tid << lp];
+        T.mx[1][tid] = srt_y[(tid << lp) + last];
         const uint32_t nb = ceil_log2(m > 1 ? m : 2u);
         const uint32_t rxr = (uint32_t)(T.mx[0][tid] - T.mn[0][tid]);
         const uint32_t ryr = (uint32_t)(T.mx[1][tid] - T.mn[1][tid]);
@@ -2100,9 +2103,6 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         }
     }
     block_sync();
-
-    // ---- sort every union's marginals (segments of P, padded with INT32_MAX)
-    sort_marginals(srt_x, srt_y, ntrip << lp, P);
 
     // ---- counts and digamma terms
     // union counts: two searches per dimension and point; a larger-part
