@@ -1424,10 +1424,24 @@ __device__ void split_item(const LaunchArgs &a, uint32_t w, int q0, uint32_t *bu
 // local items: up to 16 consecutive windows, all inside one workgroup
 // --------------------------------------------------------------------------
 
+// Digamma sums are split over this many LDS words per window, picked by the
+// lane, so that the atomics of a wave's lanes meet at most 8-way on one word
+// (the sum is exact integer arithmetic: the split changes nothing).
+constexpr int kAccSplit = 8;
+
+__device__ __forceinline__ unsigned long long acc_sum(const unsigned long long (&v)[kAccSplit])
+{
+    unsigned long long s = 0ull;
+#pragma unroll
+    for (int r = 0; r < kAccSplit; ++r)
+        s += v[r];
+    return s;
+}
+
 struct LocalShared {
     const float *x[kLocalWindows];
     const float *y[kLocalWindows];
-    unsigned long long acc[kLocalWindows];
+    unsigned long long acc[kLocalWindows][kAccSplit];
     double mi[kLocalWindows];
     uint32_t off[kLocalWindows + 1];
     uint32_t m[kLocalWindows];
@@ -1573,7 +1587,8 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
         L.y[tid] = d.y;
         L.m[tid] = d.m;
         L.query[tid] = d.query;
-        L.acc[tid] = 0ull;
+        for (int r = 0; r < kAccSplit; ++r)
+            L.acc[tid][r] = 0ull;
         L.flags[tid] = 0u;
     }
     block_sync();
@@ -1720,7 +1735,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
                 a.dbg_ey[I[q]] = (float)RY[q] * (1.0f / 4096.0f);
             }
         }
-        atomicAdd(&L.acc[w], (unsigned long long)t);
+        atomicAdd(&L.acc[w][tid & (kAccSplit - 1)], (unsigned long long)t);
     }
     block_sync();
 
@@ -1733,7 +1748,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             mi = __builtin_nan("");
             fl |= kFlagTooShort;
         } else {
-            mi = window_estimate<K>(a, m, (long long)L.acc[tid]);
+            mi = window_estimate<K>(a, m, (long long)acc_sum(L.acc[tid]));
         }
         L.mi[tid] = mi;
         L.flags[tid] = fl;
@@ -1784,7 +1799,7 @@ struct TripleShared {
     uint32_t flags[kTripleMax];
     int32_t mn[2][kTripleMax];
     int32_t mx[2][kTripleMax];
-    unsigned long long acc[kTripleMax][3];    // base, extension, union
+    unsigned long long acc[kTripleMax][3][kAccSplit];  // base, extension, union
     uint32_t P, log2P;
     uint32_t njobs;                           // part counts handed to other threads
 };
@@ -1918,7 +1933,8 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         if (tid == 0)
             T.njobs = 0u;
         for (int r = 0; r < 3; ++r)
-            T.acc[tid][r] = 0ull;
+            for (int l = 0; l < kAccSplit; ++l)
+                T.acc[tid][r][l] = 0ull;
     }
     block_sync();
     if (tid == 0) {
@@ -2213,11 +2229,12 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
                 }
             }
         }
-        atomicAdd(&T.acc[t][2], (unsigned long long)tu);
+        const int sl = tid & (kAccSplit - 1);
+        atomicAdd(&T.acc[t][2][sl], (unsigned long long)tu);
         if (tpa)
-            atomicAdd(&T.acc[t][0], (unsigned long long)tpa);
+            atomicAdd(&T.acc[t][0][sl], (unsigned long long)tpa);
         if (tpb)
-            atomicAdd(&T.acc[t][1], (unsigned long long)tpb);
+            atomicAdd(&T.acc[t][1][sl], (unsigned long long)tpb);
     }
     block_sync();
 
@@ -2234,7 +2251,7 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
                 mi = __builtin_nan("");
                 fl |= kFlagTooShort;
             } else {
-                mi = window_estimate<K>(a, (int)mw[r], (long long)T.acc[tid][r]);
+                mi = window_estimate<K>(a, (int)mw[r], (long long)acc_sum(T.acc[tid][r]));
             }
             mi3[r] = mi;
             f3[r] = fl;
