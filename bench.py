@@ -59,12 +59,12 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # launch shape it was taken with (batches per pass); keyed by workload name.
 TRAFFIC = {
     "cfg3_allpairs_64x32768_w256_s8_triples": {
-        "fetch_bytes": 1719975172, "write_bytes": 3657852446, "batches_per_pass": 16,
-        "kernel_sha256": "28ef2c30f66b6f4e19d550aabf668fa32f0a3a2feb4bb56561c7167fdc8a3270",
+        "fetch_bytes": 6755338575, "write_bytes": 10496528110, "batches_per_pass": 8,
+        "kernel_sha256": "07b2a8ffea1b0dc704fcc687eb7883233ccb8530c811169d4bf74ddd94b07220",
         "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
     "cfg2_multiscale_n65536_w32-4096_s8th": {
-        "fetch_bytes": 67028988, "write_bytes": 37277387,
-        "kernel_sha256": "28ef2c30f66b6f4e19d550aabf668fa32f0a3a2feb4bb56561c7167fdc8a3270",
+        "fetch_bytes": 71364894, "write_bytes": 39286083,
+        "kernel_sha256": "07b2a8ffea1b0dc704fcc687eb7883233ccb8530c811169d4bf74ddd94b07220",
         "source": "profiles/main_kernel_cfg2_multiscale.md"},
 }
 
@@ -183,7 +183,9 @@ def headline(args, wmi, torch, w) -> dict:
     log(f"headline: {len(rg)} runs in {len(batches)} batches, first submit {t_submit:.2f} s")
     # consecutive batches alternate between two streams, so that one batch's
     # result download overlaps its neighbour's kernels
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    # (--serial: one stream, so that per-dispatch hardware counters see one
+    # launch at a time)
+    streams = [torch.cuda.Stream()] * 2 if args.serial else [torch.cuda.Stream(), torch.cuda.Stream()]
     for _ in range(max(1, args.warmup)):
         for i, b in enumerate(batches):
             b.replay(stream=streams[i % 2], direct=True)
@@ -679,6 +681,8 @@ def main():
     ap.add_argument("--large-pairs", type=int, default=0, help="first N of the 28 pairs (0: all)")
     ap.add_argument("--no-evals", action="store_true",
                     help="skip the distance-counting pass of the headline (profiling runs)")
+    ap.add_argument("--serial", action="store_true",
+                    help="headline batches on one stream (for per-dispatch counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB elementwise kernel (HBM counter calibration)")
     args = ap.parse_args()
