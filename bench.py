@@ -60,11 +60,11 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 TRAFFIC = {
     "cfg3_allpairs_64x32768_w256_s8_triples": {
         "fetch_bytes": 6755338575, "write_bytes": 10496528110, "batches_per_pass": 8,
-        "kernel_sha256": "07b2a8ffea1b0dc704fcc687eb7883233ccb8530c811169d4bf74ddd94b07220",
+        "kernel_sha256": "31ebd685dab8ae07ce4e3710fa78d7e9c6c5c2f55b0c0f8076841d6a14bf8329",
         "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
     "cfg2_multiscale_n65536_w32-4096_s8th": {
         "fetch_bytes": 71364894, "write_bytes": 39286083,
-        "kernel_sha256": "07b2a8ffea1b0dc704fcc687eb7883233ccb8530c811169d4bf74ddd94b07220",
+        "kernel_sha256": "31ebd685dab8ae07ce4e3710fa78d7e9c6c5c2f55b0c0f8076841d6a14bf8329",
         "source": "profiles/main_kernel_cfg2_multiscale.md"},
 }
 

@@ -2656,7 +2656,7 @@ __device__ bool sweep_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
 // --------------------------------------------------------------------------
 // main: persistent loop over items
 // --------------------------------------------------------------------------
-// Two compilations per k: every item kind, at five workgroups per CU for k <=
+// Two compilations per k: every item kind, at four workgroups per CU for k <=
 // 5; and, for queues of local and triple items only, those two paths alone,
 // whose smaller register need allows eight workgroups per CU (k <= 5).
 template <int K, bool LOCAL_ONLY>
