@@ -530,6 +530,14 @@ __device__ __forceinline__ void radix_lds(uint32_t *a, int n, int lo, int passes
     block_sync();
 }
 
+// A store coherent at agent scope (a relaxed atomic store: written through
+// to memory, not held in this XCD's L2), for data another CU reads after a
+// flag.
+__device__ __forceinline__ void store_through(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Bits needed for values up to r (0 for r == 0).
 __device__ __forceinline__ int value_bits(uint32_t r) { return r ? 32 - __clz((int)r) : 0; }
 
@@ -582,21 +590,22 @@ __device__ void prep_item(const LaunchArgs &a, uint32_t w, uint32_t *buf, int32_
                 for (int g = 0; g < kLoadBatch; ++g) {
                     const int s = s0 + g * kBlock;
                     if (s < m) {
-                        out[s] = (int32_t)key[g];
-                        out[m + s] = (int32_t)((uint32_t)(grid_int(yv[g], off) - ax.min_y) << ax.nb);
+                        store_through(&out[s], (int32_t)key[g]);
+                        store_through(&out[m + s], (int32_t)((uint32_t)(grid_int(yv[g], off) - ax.min_y) << ax.nb));
                     }
                 }
             }
         } else {
             int32_t *dst = job ? out + 2 * m : out;
             for (int s = tid; s < m; s += kBlock)
-                dst[s] = (int32_t)buf[s] + mn;
+                store_through(&dst[s], (int32_t)buf[s] + mn);
         }
     }
-    // release only: write this window's sorted data back to memory before
-    // the flag is raised (the acquire half would needlessly invalidate the
-    // caches the rest of the CU's work is using)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the sorted data went to memory with agent-scope stores: once every
+    // wave's stores have completed, the flag may rise.  (A release fence
+    // would also write back the whole L2 of the XCD, the other work's dirty
+    // lines included; the split items still take an acquire before reading.)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     block_sync();
     if (threadIdx.x == 0)
         atomicExch(&a.ready[w], kReady | (ax.flags ? kReadyOffGrid : 0u) | (ax.nb << kReadyNbShift));
