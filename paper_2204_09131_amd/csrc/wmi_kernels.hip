@@ -695,6 +695,17 @@ __device__ void report_window(const LaunchArgs &a, uint32_t w, uint32_t q, doubl
     }
 }
 
+// window_estimate with psi(k) and psi(m) already at hand (fetched when the
+// item starts): the same expression, so the same rounding.
+template <int K>
+__device__ __forceinline__ double estimate_from(uint32_t est, double psi_k, double psi_m, int m, long long S)
+{
+    double Sd = (double)S * 0x1p-44;
+    if (est == 0)
+        return (psi_k - 1.0 / (double)K + psi_m) - Sd / (double)m;
+    return (psi_k + psi_m) - Sd / (double)m;
+}
+
 template <int K>
 __device__ __forceinline__ double window_estimate(const LaunchArgs &a, int m, long long S)
 {
@@ -1451,6 +1462,9 @@ struct LocalShared {
     const float *x[kLocalWindows];
     const float *y[kLocalWindows];
     unsigned long long acc[kLocalWindows][kAccSplit];
+    QDesc qd[kLocalWindows];      // each window's query, fetched when the item starts
+    double psi_m[kLocalWindows];  // psi(m) of each window, likewise
+    double psi_k;
     double mi[kLocalWindows];
     uint32_t off[kLocalWindows + 1];
     uint32_t m[kLocalWindows];
@@ -1590,28 +1604,44 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     int32_t *srt_x = reinterpret_cast<int32_t *>(buf + 2 * 1024);  // kLocalSort: sorted marginals
     int32_t *srt_y = srt_x + kLocalSort;
 
+    // descriptors, each window's query and psi values (fetched now, so that
+    // the results at the end wait on no load), and the window offsets: an
+    // exclusive scan of the even-rounded sizes (even offsets keep 16-byte
+    // candidate reads aligned) in the lanes of wave 0
+    uint32_t vm = 0u;
     if (tid < (int)nwin) {
         const WinDesc d = a.win[w0 + tid];
         L.x[tid] = d.x;
         L.y[tid] = d.y;
         L.m[tid] = d.m;
         L.query[tid] = d.query;
+        L.qd[tid] = a.qd[d.query];
+        L.psi_m[tid] = a.psi_d[min(d.m, (uint32_t)kMaxWindow)];
         for (int r = 0; r < kAccSplit; ++r)
             L.acc[tid][r] = 0ull;
         L.flags[tid] = 0u;
+        vm = d.m;
     }
-    block_sync();
-    if (tid == 0) {
-        uint32_t off = 0, mmax = 2;
-        for (uint32_t w = 0; w < nwin; ++w) {
-            L.off[w] = off;
-            off += (L.m[w] + 1u) & ~1u;  // even offsets keep 16-byte candidate reads aligned
-            mmax = max(mmax, L.m[w]);
+    if (tid < 64) {
+        static_assert(kLocalWindows <= 16, "one scan over 16 lanes");
+        const uint32_t v = (vm + 1u) & ~1u;
+        uint32_t incl = v, mmax = max(vm, 2u);
+        for (int o = 1; o < 16; o <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 16);
+            if ((tid & 15) >= o)
+                incl += u;
+            mmax = max(mmax, (uint32_t)__shfl_xor((int)mmax, o, 16));
         }
-        L.off[nwin] = off;
-        uint32_t lp = ceil_log2(mmax);
-        L.P = 1u << lp;
-        L.log2P = lp;
+        if (tid < (int)nwin)
+            L.off[tid] = incl - v;
+        if (tid == (int)nwin - 1)
+            L.off[nwin] = incl;
+        if (tid == 0) {
+            const uint32_t lp = ceil_log2(mmax);
+            L.P = 1u << lp;
+            L.log2P = lp;
+            L.psi_k = a.psi_d[K];
+        }
     }
     block_sync();
     const uint32_t total = L.off[nwin];
@@ -1622,13 +1652,16 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     uint32_t W[2];
     int I[2];
     bool act[2];
-    // slots 2t and 2t+1: window offsets are even, so both lie in one window
+    // slots 2t and 2t+1: window offsets are even, so both lie in one window,
+    // the number of later window starts at or below slot 2t
+    uint32_t w_t = 0;
+#pragma unroll
+    for (int r = 1; r < kLocalWindows; ++r)
+        w_t += (r < (int)nwin && L.off[r] <= 2u * (uint32_t)tid) ? 1u : 0u;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const uint32_t s = 2u * (uint32_t)tid + (uint32_t)q;
-        uint32_t w = 0;
-        while (w + 1 < nwin && L.off[w + 1] <= s)
-            ++w;
+        const uint32_t w = w_t;
         const int i = (int)s - (int)L.off[w];
         act[q] = s < total && i < (int)L.m[w];
         W[q] = w;
@@ -1757,7 +1790,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
             mi = __builtin_nan("");
             fl |= kFlagTooShort;
         } else {
-            mi = window_estimate<K>(a, m, (long long)acc_sum(L.acc[tid]));
+            mi = estimate_from<K>(a.estimator, L.psi_k, L.psi_m[tid], m, (long long)acc_sum(L.acc[tid]));
         }
         L.mi[tid] = mi;
         L.flags[tid] = fl;
@@ -1767,7 +1800,7 @@ __device__ void local_item(const LaunchArgs &a, uint32_t w0, uint32_t nwin, uint
     block_sync();
     if (tid < (int)nwin) {
         const uint32_t w = w0 + tid, q = L.query[tid];
-        const QDesc qd = a.qd[q];
+        const QDesc qd = L.qd[tid];
         const bool inside = qd.win0 >= w0 && qd.win0 + qd.nwin <= w0 + nwin;
         if (inside) {
             if (qd.win0 == w)
@@ -1809,6 +1842,9 @@ struct TripleShared {
     int32_t mn[2][kTripleMax];
     int32_t mx[2][kTripleMax];
     unsigned long long acc[kTripleMax][3][kAccSplit];  // base, extension, union
+    QDesc qd[kTripleMax];                     // each triple's query, fetched when the item starts
+    double psi[kTripleMax][4];                // psi(k), psi of the base, extension and union sizes
+    uint32_t query[kTripleMax];
     uint32_t P, log2P;
     uint32_t njobs;                           // part counts handed to other threads
 };
@@ -1939,6 +1975,14 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
         T.b0[tid] = (uint32_t)(de.x - du.x);
         T.nb[tid] = de.m;
         T.flags[tid] = 0u;
+        // the query and the psi values of its three sizes, fetched now so
+        // that the result at the end waits on no load
+        T.query[tid] = db.query;
+        T.qd[tid] = a.qd[db.query];
+        T.psi[tid][0] = a.psi_d[K];
+        T.psi[tid][1] = a.psi_d[min(db.m, (uint32_t)kMaxWindow)];
+        T.psi[tid][2] = a.psi_d[min(de.m, (uint32_t)kMaxWindow)];
+        T.psi[tid][3] = a.psi_d[min(du.m, (uint32_t)kMaxWindow)];
         if (tid == 0)
             T.njobs = 0u;
         for (int r = 0; r < 3; ++r)
@@ -2260,15 +2304,15 @@ __device__ void triple_item(const LaunchArgs &a, uint32_t w0, uint32_t ntrip, ui
                 mi = __builtin_nan("");
                 fl |= kFlagTooShort;
             } else {
-                mi = window_estimate<K>(a, (int)mw[r], (long long)acc_sum(T.acc[tid][r]));
+                mi = estimate_from<K>(a.estimator, T.psi[tid][0], T.psi[tid][1 + r], (int)mw[r],
+                                      (long long)acc_sum(T.acc[tid][r]));
             }
             mi3[r] = mi;
             f3[r] = fl;
             a.wmi[wb + r] = mi;
             a.wflags[wb + r] = fl;
         }
-        const uint32_t q = a.win[wb].query;
-        store_result(a, q, compose_result(a.qd[q], mi3, f3));
+        store_result(a, T.query[tid], compose_result(T.qd[tid], mi3, f3));
     }
 }
 
