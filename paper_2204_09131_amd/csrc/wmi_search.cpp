@@ -12,10 +12,13 @@
 // s_w the walk meets windows off the grid; those are evaluated in follow-up
 // batches and the walk resumes.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "wmi.h"
@@ -292,45 +295,103 @@ uint64_t bu_pick(uint64_t seed, uint64_t chunk, uint64_t i)
     return splitmix64_mix(seed + ((chunk << 32) + i + 1) * 0x9E3779B97F4A7C15ull);
 }
 
+// Evaluate a query list in batches of at most kChunkQueries queries and
+// kChunkPoints points.  The host planning of a batch costs about as much as
+// its kernels, so a step's queries go out in up to kPlanThreads batches from
+// as many host threads (the store is thread-safe): their planning overlaps
+// each other's and the earlier batches' GPU time.  Results do not depend on
+// the batching.  stats.submit_ms and wait_ms are summed over the threads.
+constexpr unsigned kPlanThreads = 8;
+constexpr uint64_t kMinThreadQueries = 8192;  // smaller batches cost more than they overlap
+
 int run_queries(wmi_store *st, const std::vector<wmi_query> &q, const wmi_params &prm, std::vector<wmi_result> &r,
                 std::vector<double> &h, wmi_search_stats &stats)
 {
     r.assign(q.size(), wmi_result());
     const bool ent = (prm.flags & WMI_SUBMIT_ENTROPY) != 0;
     h.assign(ent ? 3 * q.size() : 0, 0.0);
-    size_t i0 = 0;
-    while (i0 < q.size()) {
+    if (q.empty())
+        return WMI_OK;
+    // batch boundaries: the size caps, and at most kPlanThreads batches of at
+    // least kMinThreadQueries queries each where the caps leave fewer
+    const uint64_t per_thread = std::max<uint64_t>(
+        kMinThreadQueries, (q.size() + kPlanThreads - 1) / kPlanThreads);
+    std::vector<std::pair<size_t, size_t>> parts;
+    for (size_t i0 = 0; i0 < q.size();) {
         size_t i1 = i0;
         uint64_t pts = 0;
-        while (i1 < q.size() && i1 - i0 < kChunkQueries && (i1 == i0 || pts < kChunkPoints)) {
+        while (i1 < q.size() && i1 - i0 < std::min(kChunkQueries, per_thread) && (i1 == i0 || pts < kChunkPoints)) {
             pts += 2ull * q[i1].len + 2ull * q[i1].ext_len;
             ++i1;
         }
-        wmi_batch *bt = nullptr;
-        auto t0 = Clock::now();
-        if (int rc = wmi_submit(st, q.data() + i0, i1 - i0, &prm, nullptr, &bt))
-            return rc;
-        stats.submit_ms += ms_since(t0);
-        t0 = Clock::now();
-        int rc = wmi_read(bt, r.data() + i0);
-        if (rc == WMI_OK && ent)
-            rc = wmi_read_entropy(bt, h.data() + 3 * i0);
-        (void)wmi_batch_destroy(bt);
-        stats.wait_ms += ms_since(t0);
-        if (rc)
-            return rc;
-        stats.batches++;
-        for (size_t i = i0; i < i1; ++i) {
-            const uint64_t m = q[i].len, e = q[i].ext_len;
-            if (q[i].ext_side) {
-                stats.windows_evaluated += 3;
-                stats.ordered_pairs += triple_pairs(m, e);
-            } else {
-                stats.windows_evaluated += 1;
-                stats.ordered_pairs += window_pairs(m);
-            }
-        }
+        parts.emplace_back(i0, i1);
         i0 = i1;
+    }
+    struct Tally {
+        double submit_ms = 0.0, wait_ms = 0.0;
+        uint64_t batches = 0;
+        int rc = WMI_OK;
+        std::string msg;
+    };
+    const unsigned nt = (unsigned)std::min<size_t>(kPlanThreads, parts.size());
+    std::vector<Tally> tally(nt);
+    std::atomic<size_t> next{0};
+    std::atomic<bool> failed{false};
+    auto work = [&](unsigned t) {
+        Tally &y = tally[t];
+        for (;;) {
+            const size_t c = next.fetch_add(1);
+            if (c >= parts.size() || failed.load())
+                return;
+            const size_t i0 = parts[c].first, i1 = parts[c].second;
+            wmi_batch *bt = nullptr;
+            auto t0 = Clock::now();
+            int rc = wmi_submit(st, q.data() + i0, i1 - i0, &prm, nullptr, &bt);
+            y.submit_ms += ms_since(t0);
+            if (rc == WMI_OK) {
+                t0 = Clock::now();
+                rc = wmi_read(bt, r.data() + i0);
+                if (rc == WMI_OK && ent)
+                    rc = wmi_read_entropy(bt, h.data() + 3 * i0);
+                (void)wmi_batch_destroy(bt);
+                y.wait_ms += ms_since(t0);
+            }
+            if (rc != WMI_OK) {
+                y.rc = rc;
+                y.msg = wmi_last_error();  // this thread's message
+                failed.store(true);
+                return;
+            }
+            y.batches++;
+        }
+    };
+    if (nt == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t)
+            pool.emplace_back(work, t);
+        work(0);
+        for (auto &th : pool)
+            th.join();
+    }
+    for (const Tally &y : tally) {
+        stats.submit_ms += y.submit_ms;
+        stats.wait_ms += y.wait_ms;
+        stats.batches += y.batches;
+    }
+    for (const Tally &y : tally)
+        if (y.rc != WMI_OK)
+            return fail(y.rc, "%s", y.msg.c_str());  // on the calling thread
+    for (size_t i = 0; i < q.size(); ++i) {
+        const uint64_t m = q[i].len, e = q[i].ext_len;
+        if (q[i].ext_side) {
+            stats.windows_evaluated += 3;
+            stats.ordered_pairs += triple_pairs(m, e);
+        } else {
+            stats.windows_evaluated += 1;
+            stats.ordered_pairs += window_pairs(m);
+        }
     }
     return WMI_OK;
 }
