@@ -102,12 +102,11 @@ struct wmi_batch {
     WinDesc *d_win = nullptr;
     QDesc *d_qd = nullptr;
     Item *d_queue = nullptr;
-    size_t res_bytes = 0;  // downloaded: results, error word, entropies
+    size_t res_bytes = 0;  // results, error word, entropies (in the pinned host buffer)
     uint32_t grid = 0;
     std::vector<uint32_t> win_first_item;  // plain form: first item of each window
     std::vector<int32_t> win_prep;         // plain form: prep-list entry of a split window, or -1
-    Result *h_res = nullptr;
-    Result *d_res = nullptr;
+    Result *h_res = nullptr;  // written by the kernels straight into pinned host memory
     const double *h_hres = nullptr;  // entropies in the host buffer, or null
     RunEvents slot[kSlots];
     hipEvent_t ev_end = nullptr;  // recorded after the completion callback of the latest run
@@ -245,7 +244,7 @@ int enqueue_work(wmi_batch *b, hipStream_t s, const RunEvents *ev)
         if (ev)
             HIPCHK(st, hipEventRecord(ev->m1, s));
     }
-    HIPCHK(st, hipMemcpyAsync(b->h_res, b->d_res, b->res_bytes, hipMemcpyDeviceToHost, s));
+    // the results are already in host memory: the kernels wrote them there
     return WMI_OK;
 }
 
@@ -1037,19 +1036,27 @@ int start_batch(wmi_store *st, BatchBuild &B, const wmi_query *qs, uint64_t coun
     } else {
         write_descriptors(B, qs, count, p, b->host);
     }
+    // results, the error word and the entropies go straight from the kernels
+    // into the pinned host buffer (its device address), after the descriptor
+    // prefix: no download after a run, so consecutive batches' kernels are
+    // not kept apart by copies
     b->h_res = reinterpret_cast<Result *>(b->host + desc_bytes);
+    char *host_dev = nullptr;
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&host_dev), b->host, 0);
+    if (e != hipSuccess)
+        return bail(e, "hipHostGetDevicePointer");
+    char *res_dev = host_dev + desc_bytes;
     if (B.plain) {
         b->win_first_item = std::move(B.plan.first_item);
         b->win_prep = std::move(B.plan.wprep);
     }
     LaunchArgs &a = b->args;
-    set_args(B, st, p, count, b->dev, reinterpret_cast<Result *>(b->dev + B.o_res),
-             reinterpret_cast<uint32_t *>(b->dev + B.o_res + count * sizeof(Result)), a);
-    b->d_res = a.res;
+    set_args(B, st, p, count, b->dev, reinterpret_cast<Result *>(res_dev),
+             reinterpret_cast<uint32_t *>(res_dev + count * sizeof(Result)), a);
     b->res_bytes = B.res_bytes;
     double *d_hres = nullptr;
     if (p->flags & WMI_SUBMIT_ENTROPY) {
-        d_hres = reinterpret_cast<double *>(b->dev + B.o_hres);
+        d_hres = reinterpret_cast<double *>(res_dev + (B.o_hres - B.o_res));
         b->h_hres = reinterpret_cast<const double *>(b->host + desc_bytes + (B.o_hres - B.o_res));
     }
     set_entropy_args(B, p, count, b->dev, d_hres, b->eargs);
@@ -1353,9 +1360,10 @@ int wmi_batch_count_evals(wmi_batch *b, uint64_t *evaluated)
     if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * b->grid, s)) == hipSuccess &&
         (e = launch_clear(a, s)) == hipSuccess && (e = launch_main(a, b->grid, s)) == hipSuccess &&
         (e = hipMemcpyAsync(h.data(), cnt, sizeof(unsigned long long) * b->grid, hipMemcpyDeviceToHost, s)) ==
-            hipSuccess &&
-        (e = hipMemcpyAsync(&err, a.err, sizeof err, hipMemcpyDeviceToHost, s)) == hipSuccess)
+            hipSuccess)
         e = hipStreamSynchronize(s);
+    if (e == hipSuccess)  // the error word is in the pinned host buffer
+        std::memcpy(&err, reinterpret_cast<const char *>(b->h_res) + b->count * sizeof(Result), sizeof err);
     (void)hipFree(cnt);
     release();
     if (e != hipSuccess)
