@@ -59,11 +59,11 @@ OPS_PER_PAIR = 8   # per ordered pair: 2 differences + max (distance), k-th test
 # launch shape it was taken with (batches per pass); keyed by workload name.
 TRAFFIC = {
     "cfg3_allpairs_64x32768_w256_s8_triples": {
-        "fetch_bytes": 3578447549, "write_bytes": 9836602106, "batches_per_pass": 8,
+        "fetch_bytes": 3557529568, "write_bytes": 9822578728, "batches_per_pass": 8,
         "kernel_sha256": "7dce003a9adfec9fb62e33a0bfc36fcf2625ffbf3836cd028b28f64262bffda2",
         "source": "profiles/main_kernel_cfg3_allpairs_triples.md"},
     "cfg2_multiscale_n65536_w32-4096_s8th": {
-        "fetch_bytes": 70177916, "write_bytes": 41441647,
+        "fetch_bytes": 70279870, "write_bytes": 41440010,
         "kernel_sha256": "7dce003a9adfec9fb62e33a0bfc36fcf2625ffbf3836cd028b28f64262bffda2",
         "source": "profiles/main_kernel_cfg2_multiscale.md"},
 }
