@@ -313,7 +313,9 @@ int wmi_read_entropy(wmi_batch *batch, double *host_out);
 
 /*
  * Run the batch's work again, unchanged, on `stream` (NULL: the stream it was
- * submitted on): descriptor upload, kernels and result download.  By default
+ * submitted on): descriptor upload and kernels, which write the results
+ * straight into the batch's pinned host buffer (read with wmi_read once the
+ * batch is done).  By default
  * the sequence is captured once into a HIP graph and the graph is launched;
  * WMI_REPLAY_DIRECT enqueues the kernels one by one with events around each.
  * Runs may be pipelined: a replay does not wait for earlier runs, which are
@@ -327,7 +329,7 @@ int wmi_batch_replay(wmi_batch *batch, void *stream, uint32_t flags);
 typedef struct {
     uint32_t runs;
     int32_t mode;
-    double total_ms; /* upload + kernels + download                               */
+    double total_ms; /* upload + kernels (results land in host memory)            */
     double prep_ms;  /* prep (sorted marginals) kernel; NaN unless mode 0          */
     double main_ms;  /* main (neighbours, counts, digamma) kernel; NaN unless mode 0 */
 } wmi_timing;
